@@ -1,0 +1,168 @@
+/*
+ * cspnp -- plug-and-play ADMM reconstruction of a light-sheet z-stack from
+ * DMD-coded snapshots, on AMD Instinct MI355X (gfx950).
+ *
+ * Problem (arXiv 2511.03093, Sec. III-A, eq. (model-slice); Sec. III-C):
+ *   data b_j (j = 1..N shots, H x W pixels each) and R binary masks phi_r
+ *   shared by every shot; unknown slices v_n, n = 1..N*R, with
+ *   b_j = sum_r phi_r (.) v_{(j-1)R+r}.  The library minimises
+ *     1/2 sum_j ||b_j - sum_r phi_r v_{(j-1)R+r}||^2 + lambda sum_n psi(v_n)
+ *       + gamma/2 sum_{adjacent n} ||v_n - v_{n-1}||^2
+ *   by ADMM with the splitting v = u and scaled dual d (eq. (ADMM)),
+ *   Algorithm 1's loop: x-step, u-step (a plug-in denoiser), d-step.
+ *
+ * Memory layout (all row-major, contiguous, FP32 unless stated):
+ *   volume  x, u, d, f : float[N*R][H][W]   (slice n = (j-1)R + r, 0-based j*R+r)
+ *   frames  y          : float[N][H][W]
+ *   masks   (input)    : uint8[R][H][W], values 0 or 1
+ * Device pointers are HIP device (or managed) memory owned by the caller and
+ * must stay alive until the stream has finished the enqueued work.  Float
+ * pointers must be 4-byte aligned.  `stream` is a hipStream_t (NULL = the
+ * default stream).  All compute calls are asynchronous on `stream`.
+ *
+ * Errors: every call returns a cspnp_status.  Arguments are validated on the
+ * host before anything is enqueued; on error nothing is enqueued and
+ * cspnp_last_error() gives a thread-local description.  A device fault
+ * surfaces as CSPNP_EHIP from a later call.  The ABI never throws.
+ *
+ * Thread safety: distinct plans may be used concurrently; one plan must be
+ * used by one host thread / stream at a time (it caches launch graphs).
+ */
+#ifndef CSPNP_H
+#define CSPNP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CSPNP_VERSION 1
+
+typedef enum cspnp_status {
+  CSPNP_OK = 0,
+  CSPNP_EINVAL = 1,       /* invalid argument (null/misaligned pointer, bad shape or parameter) */
+  CSPNP_ENOMEM = 2,       /* host or device allocation failed */
+  CSPNP_EHIP = 3,         /* a HIP runtime call failed (includes earlier asynchronous faults) */
+  CSPNP_ENODEV = 4,       /* no usable gfx950 device */
+  CSPNP_EUNSUPPORTED = 5, /* valid request this build does not implement */
+  CSPNP_ENONFINITE = 6    /* non-finite value detected (only with CSPNP_FLAG_CHECK_FINITE) */
+} cspnp_status;
+
+/* z boundary of the temporal term.  PERIODIC is the paper's wrap
+ * (Sec. III-C: u_0 = u_{NR}, u_{NR+1} = u_1), each adjacent pair counted once;
+ * NEUMANN drops the wrap pair (free ends). */
+enum { CSPNP_ZBC_PERIODIC = 0, CSPNP_ZBC_NEUMANN = 1 };
+
+/* u-step denoisers (Sec. III-B, eq. (u-sub)). */
+enum { CSPNP_DENOISER_TIKHONOV = 0, CSPNP_DENOISER_TV = 1, CSPNP_DENOISER_BM3D = 2 };
+
+/* cspnp_params.flags */
+enum {
+  CSPNP_FLAG_NO_GRAPH = 1,     /* launch kernels one by one instead of replaying a captured graph */
+  CSPNP_FLAG_CHECK_FINITE = 2  /* after a solve, synchronise and fail with ENONFINITE on NaN/Inf in x */
+};
+
+/* workspace modes for cspnp_workspace_size */
+enum { CSPNP_WS_SOLVE = 0, CSPNP_WS_DENOISE = 1 };
+
+/* Problem shape: H x W pixels, R masks/slices per shot, N shots (Sec. III-A). */
+typedef struct cspnp_desc {
+  int32_t H, W;
+  int32_t R;        /* compression ratio, 1..32 */
+  int32_t N;        /* shots per volume; this build supports N = 1 */
+  int32_t zbc;      /* CSPNP_ZBC_* */
+  int32_t denoiser; /* CSPNP_DENOISER_* */
+} cspnp_desc;
+
+/* Algorithm 1's parameters (lambda, rho, gamma), the iteration count, and the
+ * TV dual-projection settings (Chambolle's step tau <= 1/4; 1/8 is the proven
+ * bound).  lambda >= 0, rho > 0, gamma >= 0, iters >= 0, tv_inner >= 0. */
+typedef struct cspnp_params {
+  double lambda;
+  double rho;
+  double gamma;
+  int32_t iters;
+  int32_t tv_inner;
+  double tv_tau;
+  double bm3d_sigma;
+  int32_t flags;
+} cspnp_params;
+
+typedef struct cspnp_plan cspnp_plan;
+
+/* Library ABI version (CSPNP_VERSION). */
+int cspnp_version(void);
+/* Static text for a status code. */
+const char* cspnp_status_string(int status);
+/* Thread-local detail of the last failed call on this thread ("" if none). */
+const char* cspnp_last_error(void);
+
+/* Create a plan for one problem shape and one mask set (Algorithm 1's
+ * "Require" inputs: the masks phi_r and the shape).  `masks` is
+ * uint8[R][H][W] with values in {0,1}, in host memory (masks_on_device = 0)
+ * or device memory (1).  The plan validates every byte (EINVAL otherwise),
+ * packs the masks into device bit-planes uint32[R][H][ceil(W/32)] (bit w%32
+ * of word w/32), and owns them.  The call is synchronous.  *out receives the
+ * plan on success and is untouched on error. */
+int cspnp_plan_create(const cspnp_desc* desc, const uint8_t* masks, int masks_on_device,
+                      void* stream, cspnp_plan** out);
+/* Free a plan and everything it owns.  NULL is accepted. */
+int cspnp_plan_destroy(cspnp_plan* plan);
+/* The plan's shape. */
+int cspnp_plan_desc(const cspnp_plan* plan, cspnp_desc* out);
+
+/* Device workspace bytes that cspnp_solve (mode CSPNP_WS_SOLVE) or
+ * cspnp_denoise (CSPNP_WS_DENOISE) needs for these parameters.  The caller
+ * allocates it (256-byte aligned) and passes it as `ws`; it may be NULL when
+ * the size is 0. */
+int cspnp_workspace_size(const cspnp_plan* plan, const cspnp_params* params, int mode,
+                         size_t* bytes);
+
+/* Forward operator, Sec. III-A / eq. (model-slice):
+ *   y[j][p] = sum_r phi_r[p] * x[j*R + r][p].
+ * x: float[N*R][H][W] (device, read), y: float[N][H][W] (device, written). */
+int cspnp_forward(const cspnp_plan* plan, const float* x, float* y, void* stream);
+
+/* Adjoint operator (the Phi^T b of eq. (v-update)):
+ *   x[j*R + r][p] = phi_r[p] * y[j][p].
+ * y: float[N][H][W] (device, read), x: float[N*R][H][W] (device, written). */
+int cspnp_adjoint(const cspnp_plan* plan, const float* y, float* x, void* stream);
+
+/* x-step (eq. (v-update), with the temporal term of Sec. III-C carried by
+ * the x-block): for every pixel p solve the N*R x N*R system
+ *   (M_p^T M_p + gamma L + rho I) x_p = M_p^T y_p + rho (u_p - d_p)
+ * with L the periodic or Neumann z-Laplacian, in FP64 registers (FP32 I/O).
+ * y: frames; u, d: volumes (read).  x_out (may be NULL) receives x, f_out (may
+ * be NULL) receives f = x + d, the datum of the next u-step.  At least one of
+ * them must be non-NULL.  Neither output may alias an input. */
+int cspnp_xupdate(const cspnp_plan* plan, const cspnp_params* params, const float* y,
+                  const float* u, const float* d, float* x_out, float* f_out, void* stream);
+
+/* u-step and d-step (eq. (u-sub) and the third line of eq. (ADMM)): every
+ * slice of f is denoised independently,
+ *   u = prox_{(lambda/rho) psi}(f),   d_out = f - u   (d_out may be NULL),
+ * with the plan's denoiser: Tikhonov u = rho f / (2 lambda + rho); TV by
+ * params->tv_inner iterations of Chambolle's dual projection with step
+ * params->tv_tau from p = 0 (theta = lambda/rho).  f, u, d_out: volumes;
+ * u and d_out must not alias f.  ws: cspnp_workspace_size(CSPNP_WS_DENOISE). */
+int cspnp_denoise(const cspnp_plan* plan, const cspnp_params* params, const float* f, float* u,
+                  float* d_out, void* ws, void* stream);
+
+/* Algorithm 1: params->iters ADMM iterations from the caller's (u, d)
+ * (zero them for a cold start; pass a previous state to resume exactly).
+ * On return (stream-ordered) x holds the last x-step result, u and d the
+ * final auxiliary and dual variables.  y: frames (read); u, d: volumes
+ * (read-write); x: volume (written; untouched when iters = 0).
+ * ws: cspnp_workspace_size(CSPNP_WS_SOLVE) bytes.  The first call with a
+ * given (parameters, pointers) captures the iteration loop into a HIP graph
+ * that later identical calls replay. */
+int cspnp_solve(const cspnp_plan* plan, const cspnp_params* params, const float* y, float* u,
+                float* d, float* x, void* ws, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CSPNP_H */

@@ -1,0 +1,292 @@
+"""ctypes binding of libcspnp (include/cspnp.h).
+
+Argument marshalling only: every computation runs in the library's HIP
+kernels.  The functions named ``cspnp_*`` mirror the C entry points one to
+one and take raw addresses; :class:`Plan` wraps them for torch tensors on the
+current HIP stream (torch supplies device memory and streams, nothing else).
+Importing this module never computes anything; :func:`load` raises when the
+library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcspnp.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENODEV, EUNSUPPORTED, ENONFINITE = range(7)
+ZBC = {"periodic": 0, "neumann": 1}
+DENOISER = {"tikhonov": 0, "tv": 1, "bm3d": 2}
+FLAG_NO_GRAPH = 1
+FLAG_CHECK_FINITE = 2
+WS_SOLVE, WS_DENOISE = 0, 1
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("H", ctypes.c_int32), ("W", ctypes.c_int32), ("R", ctypes.c_int32),
+                ("N", ctypes.c_int32), ("zbc", ctypes.c_int32), ("denoiser", ctypes.c_int32)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("lambda_", ctypes.c_double), ("rho", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("iters", ctypes.c_int32), ("tv_inner", ctypes.c_int32), ("tv_tau", ctypes.c_double),
+                ("bm3d_sigma", ctypes.c_double), ("flags", ctypes.c_int32)]
+
+
+class CspnpError(RuntimeError):
+    def __init__(self, status, func, detail):
+        self.status = status
+        super().__init__(f"{func} -> {status}: {detail}")
+
+
+_P = ctypes.c_void_p
+_SIGNATURES = {
+    "cspnp_version": ([], ctypes.c_int),
+    "cspnp_status_string": ([ctypes.c_int], ctypes.c_char_p),
+    "cspnp_last_error": ([], ctypes.c_char_p),
+    "cspnp_plan_create": ([ctypes.POINTER(Desc), _P, ctypes.c_int, _P, ctypes.POINTER(_P)], ctypes.c_int),
+    "cspnp_plan_destroy": ([_P], ctypes.c_int),
+    "cspnp_plan_desc": ([_P, ctypes.POINTER(Desc)], ctypes.c_int),
+    "cspnp_workspace_size": ([_P, ctypes.POINTER(Params), ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "cspnp_forward": ([_P, _P, _P, _P], ctypes.c_int),
+    "cspnp_adjoint": ([_P, _P, _P, _P], ctypes.c_int),
+    "cspnp_xupdate": ([_P, ctypes.POINTER(Params), _P, _P, _P, _P, _P, _P], ctypes.c_int),
+    "cspnp_denoise": ([_P, ctypes.POINTER(Params), _P, _P, _P, _P, _P], ctypes.c_int),
+    "cspnp_solve": ([_P, ctypes.POINTER(Params), _P, _P, _P, _P, _P, _P], ctypes.c_int),
+}
+
+_lib = None
+
+
+def declared_symbols():
+    """Entry points declared in include/*.h (parsed from the headers)."""
+    import re
+    inc = os.path.join(os.path.dirname(HERE), "include")
+    names = []
+    for f in sorted(os.listdir(inc)):
+        if f.endswith(".h"):
+            text = open(os.path.join(inc, f)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names += re.findall(r"\b(cspnp_[a-z0-9_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def load(path=LIB_PATH):
+    """Load libcspnp.so and declare its entry points; raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run paper_2511_03093_amd.build (hipcc, gfx950)")
+    lib = ctypes.CDLL(path)
+    for name, (args, res) in _SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def check(status, func):
+    if status != OK:
+        lib = load()
+        detail = lib.cspnp_last_error().decode()
+        raise CspnpError(status, func, detail)
+    return status
+
+
+def _call(name, *args):
+    return check(getattr(load(), name)(*args), name)
+
+
+def make_params(lam=0.05, rho=1.0, gamma=0.0, iters=1, tv_inner=10, tv_tau=0.125,
+                bm3d_sigma=9.669 / 255.0, flags=0, **_ignored):
+    return Params(float(lam), float(rho), float(gamma), int(iters), int(tv_inner), float(tv_tau),
+                  float(bm3d_sigma), int(flags))
+
+
+def params_from(p, **over):
+    """Params struct from a dict or an object with lam/rho/gamma/... attributes."""
+    if not isinstance(p, dict):
+        p = {k: getattr(p, k) for k in ("lam", "rho", "gamma", "iters", "tv_inner", "tv_tau", "bm3d_sigma")
+             if hasattr(p, k)}
+    q = dict(p)
+    q.update(over)
+    return make_params(**q)
+
+
+# --- one-to-one wrappers of the C entry points (raw addresses) -------------
+
+def cspnp_version():
+    return load().cspnp_version()
+
+
+def cspnp_status_string(status):
+    return load().cspnp_status_string(status).decode()
+
+
+def cspnp_last_error():
+    return load().cspnp_last_error().decode()
+
+
+def cspnp_plan_create(desc, masks_ptr, masks_on_device, stream):
+    out = _P()
+    _call("cspnp_plan_create", ctypes.byref(desc), _P(masks_ptr), int(masks_on_device), _P(stream),
+          ctypes.byref(out))
+    return out
+
+
+def cspnp_plan_destroy(plan):
+    _call("cspnp_plan_destroy", plan)
+
+
+def cspnp_plan_desc(plan):
+    d = Desc()
+    _call("cspnp_plan_desc", plan, ctypes.byref(d))
+    return d
+
+
+def cspnp_workspace_size(plan, params, mode):
+    n = ctypes.c_size_t()
+    _call("cspnp_workspace_size", plan, ctypes.byref(params), int(mode), ctypes.byref(n))
+    return n.value
+
+
+def cspnp_forward(plan, x, y, stream):
+    _call("cspnp_forward", plan, _P(x), _P(y), _P(stream))
+
+
+def cspnp_adjoint(plan, y, x, stream):
+    _call("cspnp_adjoint", plan, _P(y), _P(x), _P(stream))
+
+
+def cspnp_xupdate(plan, params, y, u, d, x_out, f_out, stream):
+    _call("cspnp_xupdate", plan, ctypes.byref(params), _P(y), _P(u), _P(d), _P(x_out), _P(f_out), _P(stream))
+
+
+def cspnp_denoise(plan, params, f, u, d_out, ws, stream):
+    _call("cspnp_denoise", plan, ctypes.byref(params), _P(f), _P(u), _P(d_out), _P(ws), _P(stream))
+
+
+def cspnp_solve(plan, params, y, u, d, x, ws, stream):
+    _call("cspnp_solve", plan, ctypes.byref(params), _P(y), _P(u), _P(d), _P(x), _P(ws), _P(stream))
+
+
+# --- torch-tensor convenience layer -----------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    return _torch().cuda.current_stream().cuda_stream
+
+
+def _ptr(t, name, shape=None):
+    torch = _torch()
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t.data_ptr()
+
+
+class Plan:
+    """A problem shape plus packed masks on the current device."""
+
+    def __init__(self, masks, N=1, zbc="periodic", denoiser="tv"):
+        torch = _torch()
+        if isinstance(masks, torch.Tensor):
+            m = masks.to(torch.uint8).contiguous()
+        else:
+            import numpy as np
+            m = torch.from_numpy(np.ascontiguousarray(masks, dtype=np.uint8))
+        R, H, W = m.shape
+        self.desc = Desc(H, W, R, N, ZBC[zbc], DENOISER[denoiser])
+        self.H, self.W, self.R, self.N = H, W, R, N
+        self.zbc, self.denoiser = zbc, denoiser
+        self._handle = None
+        on_dev = 1 if m.is_cuda else 0
+        self._handle = cspnp_plan_create(self.desc, m.data_ptr(), on_dev, _stream())
+
+    @property
+    def vol_shape(self):
+        return (self.N * self.R, self.H, self.W)
+
+    @property
+    def frame_shape(self):
+        return (self.N, self.H, self.W)
+
+    def close(self):
+        if self._handle is not None:
+            cspnp_plan_destroy(self._handle)
+            self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _empty(self, shape):
+        torch = _torch()
+        return torch.empty(shape, dtype=torch.float32, device="cuda")
+
+    def workspace(self, params, mode=WS_SOLVE):
+        torch = _torch()
+        n = cspnp_workspace_size(self._handle, params, mode)
+        if n == 0:
+            return None
+        return torch.empty(n + 256, dtype=torch.uint8, device="cuda")
+
+    @staticmethod
+    def _ws_ptr(ws):
+        if ws is None:
+            return None
+        p = ws.data_ptr()
+        return (p + 255) & ~255
+
+    def forward(self, x, y=None):
+        y = self._empty(self.frame_shape) if y is None else y
+        cspnp_forward(self._handle, _ptr(x, "x", self.vol_shape), _ptr(y, "y", self.frame_shape), _stream())
+        return y
+
+    def adjoint(self, y, x=None):
+        x = self._empty(self.vol_shape) if x is None else x
+        cspnp_adjoint(self._handle, _ptr(y, "y", self.frame_shape), _ptr(x, "x", self.vol_shape), _stream())
+        return x
+
+    def xupdate(self, params, y, u, d, want_x=True, want_f=True):
+        x = self._empty(self.vol_shape) if want_x else None
+        f = self._empty(self.vol_shape) if want_f else None
+        cspnp_xupdate(self._handle, params, _ptr(y, "y", self.frame_shape), _ptr(u, "u", self.vol_shape),
+                      _ptr(d, "d", self.vol_shape), _ptr(x, "x_out") if x is not None else None,
+                      _ptr(f, "f_out") if f is not None else None, _stream())
+        return x, f
+
+    def denoise(self, params, f, want_d=True, ws=None):
+        u = self._empty(self.vol_shape)
+        d = self._empty(self.vol_shape) if want_d else None
+        ws = self.workspace(params, WS_DENOISE) if ws is None else ws
+        cspnp_denoise(self._handle, params, _ptr(f, "f", self.vol_shape), _ptr(u, "u"),
+                      _ptr(d, "d_out") if d is not None else None, self._ws_ptr(ws), _stream())
+        return u, d
+
+    def solve(self, params, y, u=None, d=None, x=None, ws=None):
+        """Run params.iters iterations in place on (u, d); returns (x, u, d)."""
+        torch = _torch()
+        u = torch.zeros(self.vol_shape, dtype=torch.float32, device="cuda") if u is None else u
+        d = torch.zeros(self.vol_shape, dtype=torch.float32, device="cuda") if d is None else d
+        x = self._empty(self.vol_shape) if x is None else x
+        ws = self.workspace(params, WS_SOLVE) if ws is None else ws
+        cspnp_solve(self._handle, params, _ptr(y, "y", self.frame_shape), _ptr(u, "u", self.vol_shape),
+                    _ptr(d, "d", self.vol_shape), _ptr(x, "x", self.vol_shape), self._ws_ptr(ws), _stream())
+        return x, u, d

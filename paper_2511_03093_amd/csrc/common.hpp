@@ -1,0 +1,101 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/cspnp.h"
+
+#define CSPNP_API extern "C" __attribute__((visibility("default")))
+
+namespace cspnp {
+
+constexpr int kMaxR = 32;
+
+// Error text of the last failed call on this thread.
+void set_error(const std::string& msg);
+void clear_error();
+int fail(int status, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+#define CSPNP_HIP(call)                                \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) return hip_fail(e_, #call);  \
+  } while (0)
+
+// Per-pixel z-solve constants for T = rho I + gamma L_N (free-ends chain),
+// LDL^T factored in FP64 on the host: T = L D L^T with unit lower bidiagonal L
+// (sub-diagonal l[i], i >= 1) and D = diag(1/invd[i]).  For the periodic chain
+// the wrap pair adds gamma w w^T with w = e_0 - e_{R-1}; c = T^{-1} w and
+// wc = w^T c are precomputed for the rank-2 Woodbury correction.
+struct ZSolve {
+  double l[kMaxR];
+  double invd[kMaxR];
+  double c[kMaxR];
+  double wc;
+  double rho;
+  double gamma;
+  int32_t periodic;  // 1 when the wrap term is present (periodic, R >= 2, gamma > 0)
+  int32_t pad;
+};
+
+ZSolve make_zsolve(int R, int zbc, double rho, double gamma);
+
+// TV dual-projection settings for one launch.
+struct TvArgs {
+  float theta;    // lambda / rho
+  float inv_theta;
+  float tau;
+  int32_t iters;  // inner iterations fused into this launch
+};
+
+struct GraphCache {
+  std::vector<uint8_t> key;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+}  // namespace cspnp
+
+struct cspnp_plan {
+  cspnp_desc desc;
+  int device = 0;
+  int Wq = 0;                    // 32-bit words per bit-plane row
+  uint32_t* bits = nullptr;      // device uint32[R][H][Wq]
+  hipStream_t capture_stream = nullptr;
+  cspnp::GraphCache graph;
+  ~cspnp_plan();
+};
+
+namespace cspnp {
+
+int validate_plan(const cspnp_plan* plan);
+int validate_params(const cspnp_plan* plan, const cspnp_params* p);
+int check_ptr(const void* p, const char* name);
+
+// Kernel launchers (enqueue only; arguments already validated).
+hipError_t launch_forward(const cspnp_plan& pl, const float* x, float* y, hipStream_t s);
+hipError_t launch_adjoint(const cspnp_plan& pl, const float* y, float* x, hipStream_t s);
+// x-step; writes x_out and/or f_out = x + d.  When tik_lam_over >= 0 the
+// Tikhonov prox and d-step are fused: u_out = rho f/(2 lambda + rho), d_out = f - u.
+hipError_t launch_xupdate(const cspnp_plan& pl, const ZSolve& zs, const float* y, const float* u,
+                          const float* d, float* x_out, float* f_out, hipStream_t s);
+hipError_t launch_xupdate_tikhonov(const cspnp_plan& pl, const ZSolve& zs, double lambda,
+                                   const float* y, float* u, float* d, float* x_out,
+                                   hipStream_t s);
+hipError_t launch_tikhonov(const cspnp_plan& pl, double lambda, double rho, const float* f,
+                           float* u, float* d_out, hipStream_t s);
+// TV prox of every slice of f; ws holds the dual field between passes when
+// the inner iterations do not fit one fused launch.
+size_t tv_workspace_bytes(const cspnp_plan& pl, int tv_inner);
+hipError_t launch_tv(const cspnp_plan& pl, double lambda, double rho, int tv_inner, double tau,
+                     const float* f, float* u, float* d_out, void* ws, hipStream_t s);
+
+}  // namespace cspnp

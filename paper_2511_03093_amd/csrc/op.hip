@@ -1,0 +1,115 @@
+// Forward operator and adjoint of the DMD-coded acquisition (Sec. III-A,
+// eq. (model-slice)), on bit-packed masks.  HBM-bound streaming kernels: each
+// thread owns VEC consecutive pixels of one row; 64-lane waves read 64*VEC
+// consecutive floats per slice, and the VEC mask bits of a slice share one
+// 32-bit word of the bit-plane.
+#include "common.hpp"
+
+namespace cspnp {
+
+namespace {
+
+constexpr int kOpThreads = 256;
+
+template <int VEC>
+struct Vec;
+template <>
+struct Vec<1> {
+  using T = float;
+  static __device__ float get(const T& v, int) { return v; }
+  static __device__ void set(T& v, int, float x) { v = x; }
+};
+template <>
+struct Vec<4> {
+  using T = float4;
+  static __device__ float get(const T& v, int i) { return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w; }
+  static __device__ void set(T& v, int i, float x) {
+    if (i == 0) v.x = x; else if (i == 1) v.y = x; else if (i == 2) v.z = x; else v.w = x;
+  }
+};
+
+// y[j][p] = sum_r bit_r(p) * x[j*R + r][p]
+template <int VEC>
+__global__ __launch_bounds__(kOpThreads) void forward_kernel(const float* __restrict__ x,
+                                                             float* __restrict__ y,
+                                                             const uint32_t* __restrict__ bits,
+                                                             int H, int W, int Wq, int R, int N) {
+  using V = Vec<VEC>;
+  const int w0 = (blockIdx.x * kOpThreads + threadIdx.x) * VEC;
+  const int h = blockIdx.y;
+  if (w0 >= W) return;
+  const size_t HW = (size_t)H * W;
+  const size_t p = (size_t)h * W + w0;
+  for (int j = 0; j < N; ++j) {
+    float acc[VEC];
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) acc[i] = 0.f;
+    for (int r = 0; r < R; ++r) {
+      const uint32_t word = bits[((size_t)r * H + h) * Wq + (w0 >> 5)] >> (w0 & 31);
+      const typename V::T xv = *reinterpret_cast<const typename V::T*>(x + (size_t)(j * R + r) * HW + p);
+#pragma unroll
+      for (int i = 0; i < VEC; ++i) acc[i] += ((word >> i) & 1u) ? V::get(xv, i) : 0.f;
+    }
+    typename V::T out;
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) V::set(out, i, acc[i]);
+    *reinterpret_cast<typename V::T*>(y + (size_t)j * HW + p) = out;
+  }
+}
+
+// x[j*R + r][p] = bit_r(p) * y[j][p]
+template <int VEC>
+__global__ __launch_bounds__(kOpThreads) void adjoint_kernel(const float* __restrict__ y,
+                                                             float* __restrict__ x,
+                                                             const uint32_t* __restrict__ bits,
+                                                             int H, int W, int Wq, int R, int N) {
+  using V = Vec<VEC>;
+  const int w0 = (blockIdx.x * kOpThreads + threadIdx.x) * VEC;
+  const int h = blockIdx.y;
+  if (w0 >= W) return;
+  const size_t HW = (size_t)H * W;
+  const size_t p = (size_t)h * W + w0;
+  for (int j = 0; j < N; ++j) {
+    const typename V::T yv = *reinterpret_cast<const typename V::T*>(y + (size_t)j * HW + p);
+    for (int r = 0; r < R; ++r) {
+      const uint32_t word = bits[((size_t)r * H + h) * Wq + (w0 >> 5)] >> (w0 & 31);
+      typename V::T out;
+#pragma unroll
+      for (int i = 0; i < VEC; ++i) V::set(out, i, ((word >> i) & 1u) ? V::get(yv, i) : 0.f);
+      *reinterpret_cast<typename V::T*>(x + (size_t)(j * R + r) * HW + p) = out;
+    }
+  }
+}
+
+bool vec4_ok(int W, const void* a, const void* b) {
+  return (W % 4 == 0) && (reinterpret_cast<uintptr_t>(a) % 16 == 0) &&
+         (reinterpret_cast<uintptr_t>(b) % 16 == 0);
+}
+
+}  // namespace
+
+hipError_t launch_forward(const cspnp_plan& pl, const float* x, float* y, hipStream_t s) {
+  const auto& d = pl.desc;
+  if (vec4_ok(d.W, x, y)) {
+    dim3 grid((d.W / 4 + kOpThreads - 1) / kOpThreads, d.H);
+    hipLaunchKernelGGL(forward_kernel<4>, grid, dim3(kOpThreads), 0, s, x, y, pl.bits, d.H, d.W, pl.Wq, d.R, d.N);
+  } else {
+    dim3 grid((d.W + kOpThreads - 1) / kOpThreads, d.H);
+    hipLaunchKernelGGL(forward_kernel<1>, grid, dim3(kOpThreads), 0, s, x, y, pl.bits, d.H, d.W, pl.Wq, d.R, d.N);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint(const cspnp_plan& pl, const float* y, float* x, hipStream_t s) {
+  const auto& d = pl.desc;
+  if (vec4_ok(d.W, x, y)) {
+    dim3 grid((d.W / 4 + kOpThreads - 1) / kOpThreads, d.H);
+    hipLaunchKernelGGL(adjoint_kernel<4>, grid, dim3(kOpThreads), 0, s, y, x, pl.bits, d.H, d.W, pl.Wq, d.R, d.N);
+  } else {
+    dim3 grid((d.W + kOpThreads - 1) / kOpThreads, d.H);
+    hipLaunchKernelGGL(adjoint_kernel<1>, grid, dim3(kOpThreads), 0, s, y, x, pl.bits, d.H, d.W, pl.Wq, d.R, d.N);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace cspnp

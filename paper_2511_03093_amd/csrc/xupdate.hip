@@ -1,0 +1,217 @@
+// x-step of the ADMM (eq. (v-update)) with the temporal term of Sec. III-C
+// folded in: for every pixel p solve
+//     (m m^T + gamma L + rho I) x = m y + rho (u - d)
+// where m in {0,1}^R are the pixel's mask bits and L the z-Laplacian.
+// Write A = T + U U^T with T = rho I + gamma L_N (the free-ends chain, a
+// tridiagonal matrix shared by all pixels and LDL^T-factored on the host) and
+// U = [m] (Neumann) or U = [m, sqrt(gamma) w], w = e_0 - e_{R-1} (periodic:
+// the wrap pair).  The Woodbury identity (the paper's eq. (Woodbury), here
+// with a 2 x 2 capacitance matrix) gives
+//     x = a - alpha b - beta c,  a = T^{-1} rhs, b = T^{-1} m, c = T^{-1} w,
+// with (alpha, beta) from the 2 x 2 system.  At gamma = 0, T = rho I and this is
+// exactly the paper's element-wise update (end of Sec. III-B).
+// One thread per pixel, the z-vector in FP64 registers, FP32 in/out; the
+// kernel streams u, d (8 B/voxel) and writes f = x + d (4 B/voxel): HBM-bound.
+#include "common.hpp"
+
+namespace cspnp {
+
+namespace {
+
+constexpr int kXuBlockX = 64;
+constexpr int kXuBlockY = 4;
+
+template <int R>
+__device__ __forceinline__ void tsolve(const ZSolve& z, double (&v)[R]) {
+  // L z = v, then z *= D^{-1}, then L^T x = z
+#pragma unroll
+  for (int i = 1; i < R; ++i) v[i] = fma(-z.l[i], v[i - 1], v[i]);
+  v[R - 1] *= z.invd[R - 1];
+#pragma unroll
+  for (int i = R - 2; i >= 0; --i) v[i] = fma(-z.l[i + 1], v[i + 1], v[i] * z.invd[i]);
+}
+
+// Solves the pixel system; on return a[] holds x.
+template <int R>
+__device__ __forceinline__ void pixel_solve(const ZSolve& z, uint32_t m, double (&a)[R]) {
+  double b[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) b[r] = (double)((m >> r) & 1u);
+  tsolve<R>(z, a);
+  tsolve<R>(z, b);
+  double mTa = 0.0, mTb = 0.0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if ((m >> r) & 1u) {
+      mTa += a[r];
+      mTb += b[r];
+    }
+  }
+  if (z.periodic) {
+    const double g = z.gamma;
+    const double wTa = a[0] - a[R - 1];
+    const double wTb = b[0] - b[R - 1];
+    // [1 + mTb, wTb; g wTb, 1 + g wc] [alpha; beta'] = [mTa; g wTa], beta' = sqrt(g) beta
+    const double c11 = 1.0 + mTb, c12 = wTb, c21 = g * wTb, c22 = 1.0 + g * z.wc;
+    const double r1 = mTa, r2 = g * wTa;
+    const double inv = 1.0 / (c11 * c22 - c12 * c21);
+    const double alpha = (r1 * c22 - c12 * r2) * inv;
+    const double beta = (c11 * r2 - c21 * r1) * inv;
+#pragma unroll
+    for (int r = 0; r < R; ++r) a[r] = a[r] - alpha * b[r] - beta * z.c[r];
+  } else {
+    const double alpha = mTa / (1.0 + mTb);
+#pragma unroll
+    for (int r = 0; r < R; ++r) a[r] = fma(-alpha, b[r], a[r]);
+  }
+}
+
+template <int R>
+__device__ __forceinline__ uint32_t load_bits(const uint32_t* __restrict__ bits, int H, int Wq,
+                                              int h, int w) {
+  uint32_t m = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) m |= ((bits[((size_t)r * H + h) * Wq + (w >> 5)] >> (w & 31)) & 1u) << r;
+  return m;
+}
+
+template <int R>
+__global__ __launch_bounds__(kXuBlockX* kXuBlockY) void xupdate_kernel(
+    const ZSolve z, const uint32_t* __restrict__ bits, int H, int W, int Wq,
+    const float* __restrict__ y, const float* __restrict__ u, const float* __restrict__ d,
+    float* __restrict__ x_out, float* __restrict__ f_out) {
+  const int w = blockIdx.x * kXuBlockX + threadIdx.x;
+  const int h = blockIdx.y * kXuBlockY + threadIdx.y;
+  if (w >= W || h >= H) return;
+  const size_t HW = (size_t)H * W;
+  const size_t p = (size_t)h * W + w;
+  const uint32_t m = load_bits<R>(bits, H, Wq, h, w);
+  const double yv = (double)y[p];
+  double a[R];
+  float dv[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const float ur = u[r * HW + p];
+    dv[r] = d[r * HW + p];
+    a[r] = z.rho * ((double)ur - (double)dv[r]);
+    if ((m >> r) & 1u) a[r] += yv;
+  }
+  pixel_solve<R>(z, m, a);
+  if (x_out) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) x_out[r * HW + p] = (float)a[r];
+  }
+  if (f_out) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) f_out[r * HW + p] = (float)(a[r] + (double)dv[r]);
+  }
+}
+
+// x-step fused with the Tikhonov u-step and the d-step (in place on u, d):
+//   f = x + d,  u = rho f / (2 lambda + rho),  d = f - u.
+template <int R>
+__global__ __launch_bounds__(kXuBlockX* kXuBlockY) void xupdate_tikhonov_kernel(
+    const ZSolve z, double shrink, const uint32_t* __restrict__ bits, int H, int W, int Wq,
+    const float* __restrict__ y, float* __restrict__ u, float* __restrict__ d,
+    float* __restrict__ x_out) {
+  const int w = blockIdx.x * kXuBlockX + threadIdx.x;
+  const int h = blockIdx.y * kXuBlockY + threadIdx.y;
+  if (w >= W || h >= H) return;
+  const size_t HW = (size_t)H * W;
+  const size_t p = (size_t)h * W + w;
+  const uint32_t m = load_bits<R>(bits, H, Wq, h, w);
+  const double yv = (double)y[p];
+  double a[R];
+  float dv[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const float ur = u[r * HW + p];
+    dv[r] = d[r * HW + p];
+    a[r] = z.rho * ((double)ur - (double)dv[r]);
+    if ((m >> r) & 1u) a[r] += yv;
+  }
+  pixel_solve<R>(z, m, a);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (x_out) x_out[r * HW + p] = (float)a[r];
+    const double f = a[r] + (double)dv[r];
+    const double un = shrink * f;
+    u[r * HW + p] = (float)un;
+    d[r * HW + p] = (float)(f - un);
+  }
+}
+
+// Tikhonov prox of a given f (unfused u-step + d-step).
+__global__ __launch_bounds__(256) void tikhonov_kernel(float shrink, size_t n, const float* __restrict__ f,
+                                                       float* __restrict__ u, float* __restrict__ d_out) {
+  for (size_t i = blockIdx.x * 256ull + threadIdx.x; i < n; i += (size_t)gridDim.x * 256ull) {
+    const float fv = f[i];
+    const float uv = shrink * fv;
+    u[i] = uv;
+    if (d_out) d_out[i] = fv - uv;
+  }
+}
+
+template <int R>
+hipError_t launch_r(const cspnp_plan& pl, const ZSolve& zs, const float* y, const float* u,
+                    const float* d, float* x_out, float* f_out, hipStream_t s) {
+  const auto& de = pl.desc;
+  dim3 block(kXuBlockX, kXuBlockY);
+  dim3 grid((de.W + kXuBlockX - 1) / kXuBlockX, (de.H + kXuBlockY - 1) / kXuBlockY);
+  hipLaunchKernelGGL(xupdate_kernel<R>, grid, block, 0, s, zs, pl.bits, de.H, de.W, pl.Wq, y, u, d,
+                     x_out, f_out);
+  return hipGetLastError();
+}
+
+template <int R>
+hipError_t launch_tik_r(const cspnp_plan& pl, const ZSolve& zs, double shrink, const float* y,
+                        float* u, float* d, float* x_out, hipStream_t s) {
+  const auto& de = pl.desc;
+  dim3 block(kXuBlockX, kXuBlockY);
+  dim3 grid((de.W + kXuBlockX - 1) / kXuBlockX, (de.H + kXuBlockY - 1) / kXuBlockY);
+  hipLaunchKernelGGL(xupdate_tikhonov_kernel<R>, grid, block, 0, s, zs, shrink, pl.bits, de.H, de.W,
+                     pl.Wq, y, u, d, x_out);
+  return hipGetLastError();
+}
+
+template <int... Rs>
+struct RTable {
+  template <typename F>
+  static hipError_t dispatch(int R, F&& f) {
+    hipError_t e = hipErrorInvalidValue;
+    ((R == Rs ? (e = f(std::integral_constant<int, Rs>{}), true) : false) || ...);
+    return e;
+  }
+};
+using AllR = RTable<1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19, 20, 21, 22, 23,
+                    24, 25, 26, 27, 28, 29, 30, 31, 32>;
+
+}  // namespace
+
+hipError_t launch_xupdate(const cspnp_plan& pl, const ZSolve& zs, const float* y, const float* u,
+                          const float* d, float* x_out, float* f_out, hipStream_t s) {
+  return AllR::dispatch(pl.desc.R, [&](auto rc) {
+    return launch_r<decltype(rc)::value>(pl, zs, y, u, d, x_out, f_out, s);
+  });
+}
+
+hipError_t launch_xupdate_tikhonov(const cspnp_plan& pl, const ZSolve& zs, double lambda,
+                                   const float* y, float* u, float* d, float* x_out,
+                                   hipStream_t s) {
+  const double shrink = zs.rho / (2.0 * lambda + zs.rho);
+  return AllR::dispatch(pl.desc.R, [&](auto rc) {
+    return launch_tik_r<decltype(rc)::value>(pl, zs, shrink, y, u, d, x_out, s);
+  });
+}
+
+hipError_t launch_tikhonov(const cspnp_plan& pl, double lambda, double rho, const float* f,
+                           float* u, float* d_out, hipStream_t s) {
+  const size_t n = (size_t)pl.desc.N * pl.desc.R * pl.desc.H * pl.desc.W;
+  const float shrink = (float)(rho / (2.0 * lambda + rho));
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(tikhonov_kernel, dim3((unsigned)blocks), dim3(256), 0, s, shrink, n, f, u, d_out);
+  return hipGetLastError();
+}
+
+}  // namespace cspnp

@@ -1,0 +1,74 @@
+"""The C-ABI library loads without a GPU, exports every declared entry point,
+and rejects invalid arguments on the host before touching a device."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_2511_03093_amd import cspnp
+
+
+def test_exports_every_declared_symbol(lib):
+    names = cspnp.declared_symbols()
+    assert "cspnp_solve" in names and "cspnp_plan_create" in names
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert lib.cspnp_version() == 1
+
+
+def test_status_strings(lib):
+    for s in range(7):
+        assert cspnp.cspnp_status_string(s).startswith("CSPNP_")
+
+
+def _create(desc, masks):
+    out = ctypes.c_void_p()
+    ptr = masks.ctypes.data if masks is not None else None
+    st = cspnp.load().cspnp_plan_create(ctypes.byref(desc) if desc is not None else None,
+                                        ctypes.c_void_p(ptr), 0, None, ctypes.byref(out))
+    return st, out
+
+
+def test_plan_create_validation(lib):
+    m = np.zeros((4, 8, 8), np.uint8)
+    st, _ = _create(None, m)
+    assert st == cspnp.EINVAL and "desc" in cspnp.cspnp_last_error()
+    st, _ = _create(cspnp.Desc(8, 8, 0, 1, 0, 1), m)
+    assert st == cspnp.EINVAL and "R" in cspnp.cspnp_last_error()
+    st, _ = _create(cspnp.Desc(8, 8, 33, 1, 0, 1), m)
+    assert st == cspnp.EINVAL
+    st, _ = _create(cspnp.Desc(0, 8, 4, 1, 0, 1), m)
+    assert st == cspnp.EINVAL
+    st, _ = _create(cspnp.Desc(8, 8, 4, 2, 0, 1), m)
+    assert st == cspnp.EUNSUPPORTED
+    st, _ = _create(cspnp.Desc(8, 8, 4, 1, 7, 1), m)
+    assert st == cspnp.EINVAL and "zbc" in cspnp.cspnp_last_error()
+    st, _ = _create(cspnp.Desc(8, 8, 4, 1, 0, 9), m)
+    assert st == cspnp.EINVAL
+    st, _ = _create(cspnp.Desc(8, 8, 4, 1, 0, 1), None)
+    assert st == cspnp.EINVAL and "masks" in cspnp.cspnp_last_error()
+    bad = m.copy()
+    bad[2, 3, 4] = 2
+    st, _ = _create(cspnp.Desc(8, 8, 4, 1, 0, 1), bad)
+    assert st == cspnp.EINVAL and "mask byte" in cspnp.cspnp_last_error()
+
+
+def test_null_plan_is_rejected(lib):
+    p = cspnp.make_params()
+    assert lib.cspnp_forward(None, None, None, None) == cspnp.EINVAL
+    assert lib.cspnp_adjoint(None, None, None, None) == cspnp.EINVAL
+    assert lib.cspnp_solve(None, ctypes.byref(p), None, None, None, None, None, None) == cspnp.EINVAL
+    assert lib.cspnp_xupdate(None, ctypes.byref(p), None, None, None, None, None, None) == cspnp.EINVAL
+    assert lib.cspnp_denoise(None, ctypes.byref(p), None, None, None, None, None) == cspnp.EINVAL
+    n = ctypes.c_size_t()
+    assert lib.cspnp_workspace_size(None, ctypes.byref(p), 0, ctypes.byref(n)) == cspnp.EINVAL
+    assert lib.cspnp_plan_destroy(None) == cspnp.OK
+
+
+def test_no_device_reports_enodev(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    m = np.zeros((4, 8, 8), np.uint8)
+    st, _ = _create(cspnp.Desc(8, 8, 4, 1, 0, 1), m)
+    assert st == cspnp.ENODEV
