@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=8, help="oracle iterations in the CPU sample")
     ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -95,6 +97,7 @@ def main():
     nvox = NR * H * W
     plan = cspnp.Plan(prob.masks, zbc=pd["zbc"], denoiser=pd["denoiser"])
     params = cspnp.params_from(pd)
+    tuned = plan.autotune(params)  # launch shapes timed on this device (not part of a step)
     y = torch.from_numpy(prob.y).cuda()
     u = torch.zeros((NR, H, W), device="cuda")
     d = torch.zeros((NR, H, W), device="cuda")
@@ -174,8 +177,16 @@ def main():
                    "H": H, "W": W, "B": R, "iters": iters, "tv_inner": pd["tv_inner"]},
         "roofline": roofline,
         "kernels": kernels,
+        "tuning": {"tv_shape": tuned[0], "tv_tile": list(cspnp.cspnp_tv_shape_info(tuned[0])),
+                   "xu_block": tuned[1]},
         "wall_s_timed": wall,
     }
+    if a.copy_probe_mib:
+        n = a.copy_probe_mib * (1 << 20) // 4
+        src = torch.ones(n, device="cuda")
+        dst = torch.empty(n, device="cuda")
+        t_cp = time_launches(lambda: dst.copy_(src), 5)
+        out["copy_probe"] = {"MiB": a.copy_probe_mib, "us": t_cp * 1e6, "GB/s": 2 * n * 4 / t_cp / 1e9}
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, pd, a.cpu_iters)
     print(json.dumps(out), flush=True)

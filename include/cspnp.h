@@ -161,6 +161,33 @@ int cspnp_denoise(const cspnp_plan* plan, const cspnp_params* params, const floa
 int cspnp_solve(const cspnp_plan* plan, const cspnp_params* params, const float* y, float* u,
                 float* d, float* x, void* ws, void* stream);
 
+/* ---- launch-shape tuning ------------------------------------------------ */
+
+/* A plan's launch shapes: an index into the TV tile-shape table and into the
+ * x-update block-shape table.  Shapes change only speed, never results
+ * beyond FP32 rounding order (the TV result is identical: every pixel's
+ * arithmetic is the same whatever the tile). */
+typedef struct cspnp_tuning {
+  int32_t tv_shape;
+  int32_t xu_block;
+} cspnp_tuning;
+
+/* Number of TV tile shapes and x-update block shapes. */
+int cspnp_tuning_candidates(int32_t* n_tv_shapes, int32_t* n_xu_blocks);
+/* Tile size (pixels) and workgroup size of TV shape `index`. */
+int cspnp_tv_shape_info(int32_t index, int32_t* tile_cols, int32_t* tile_rows, int32_t* threads);
+/* Read / set a plan's shapes (EINVAL for an index out of range).  Setting
+ * drops the plan's cached solve graph. */
+int cspnp_plan_get_tuning(const cspnp_plan* plan, cspnp_tuning* out);
+int cspnp_plan_set_tuning(cspnp_plan* plan, const cspnp_tuning* tuning);
+/* Choose the plan's shapes by timing every candidate with HIP events on
+ * `stream` for these parameters (synchronous; allocates and frees scratch
+ * volumes).  With cache_path != NULL a JSON file keyed by (device arch, H, W,
+ * R, N, z boundary, denoiser, TV inner count) is read first (unless force is
+ * non-zero) and updated afterwards. */
+int cspnp_autotune(cspnp_plan* plan, const cspnp_params* params, const char* cache_path, int force,
+                   void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -34,6 +34,10 @@ class Params(ctypes.Structure):
                 ("bm3d_sigma", ctypes.c_double), ("flags", ctypes.c_int32)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("tv_shape", ctypes.c_int32), ("xu_block", ctypes.c_int32)]
+
+
 class CspnpError(RuntimeError):
     def __init__(self, status, func, detail):
         self.status = status
@@ -54,6 +58,12 @@ _SIGNATURES = {
     "cspnp_xupdate": ([_P, ctypes.POINTER(Params), _P, _P, _P, _P, _P, _P], ctypes.c_int),
     "cspnp_denoise": ([_P, ctypes.POINTER(Params), _P, _P, _P, _P, _P], ctypes.c_int),
     "cspnp_solve": ([_P, ctypes.POINTER(Params), _P, _P, _P, _P, _P, _P], ctypes.c_int),
+    "cspnp_tuning_candidates": ([ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "cspnp_tv_shape_info": ([ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                             ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "cspnp_plan_get_tuning": ([_P, ctypes.POINTER(Tuning)], ctypes.c_int),
+    "cspnp_plan_set_tuning": ([_P, ctypes.POINTER(Tuning)], ctypes.c_int),
+    "cspnp_autotune": ([_P, ctypes.POINTER(Params), ctypes.c_char_p, ctypes.c_int, _P], ctypes.c_int),
 }
 
 _lib = None
@@ -173,6 +183,34 @@ def cspnp_solve(plan, params, y, u, d, x, ws, stream):
     _call("cspnp_solve", plan, ctypes.byref(params), _P(y), _P(u), _P(d), _P(x), _P(ws), _P(stream))
 
 
+def cspnp_tuning_candidates():
+    a, b = ctypes.c_int32(), ctypes.c_int32()
+    _call("cspnp_tuning_candidates", ctypes.byref(a), ctypes.byref(b))
+    return a.value, b.value
+
+
+def cspnp_tv_shape_info(index):
+    c, r, t = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _call("cspnp_tv_shape_info", int(index), ctypes.byref(c), ctypes.byref(r), ctypes.byref(t))
+    return c.value, r.value, t.value
+
+
+def cspnp_plan_get_tuning(plan):
+    t = Tuning()
+    _call("cspnp_plan_get_tuning", plan, ctypes.byref(t))
+    return t.tv_shape, t.xu_block
+
+
+def cspnp_plan_set_tuning(plan, tv_shape, xu_block):
+    t = Tuning(int(tv_shape), int(xu_block))
+    _call("cspnp_plan_set_tuning", plan, ctypes.byref(t))
+
+
+def cspnp_autotune(plan, params, cache_path, force, stream):
+    cp = cache_path.encode() if cache_path else None
+    _call("cspnp_autotune", plan, ctypes.byref(params), cp, int(force), _P(stream))
+
+
 # --- torch-tensor convenience layer -----------------------------------------
 
 def _torch():
@@ -279,6 +317,16 @@ class Plan:
         cspnp_denoise(self._handle, params, _ptr(f, "f", self.vol_shape), _ptr(u, "u"),
                       _ptr(d, "d_out") if d is not None else None, self._ws_ptr(ws), _stream())
         return u, d
+
+    def tuning(self):
+        return cspnp_plan_get_tuning(self._handle)
+
+    def set_tuning(self, tv_shape, xu_block):
+        cspnp_plan_set_tuning(self._handle, tv_shape, xu_block)
+
+    def autotune(self, params, cache_path=None, force=False):
+        cspnp_autotune(self._handle, params, cache_path, force, _stream())
+        return self.tuning()
 
     def solve(self, params, y, u=None, d=None, x=None, ws=None):
         """Run params.iters iterations in place on (u, d); returns (x, u, d)."""

@@ -56,6 +56,11 @@ struct TvArgs {
   int32_t iters;  // inner iterations fused into this launch
 };
 
+struct TvShapeInfo {
+  int cx, s, nw;  // lane columns, rows per lane, waves per workgroup
+  int cols, rows; // tile size in pixels
+};
+
 struct GraphCache {
   std::vector<uint8_t> key;
   hipGraph_t graph = nullptr;
@@ -71,6 +76,8 @@ struct cspnp_plan {
   uint32_t* bits = nullptr;      // device uint32[R][H][Wq]
   hipStream_t capture_stream = nullptr;
   cspnp::GraphCache graph;
+  int tv_shape = 0;  // index into the TV tile-shape table
+  int xu_block = 0;  // index into the x-update block-shape table
   ~cspnp_plan();
 };
 
@@ -97,5 +104,12 @@ hipError_t launch_tikhonov(const cspnp_plan& pl, double lambda, double rho, cons
 size_t tv_workspace_bytes(const cspnp_plan& pl, int tv_inner);
 hipError_t launch_tv(const cspnp_plan& pl, double lambda, double rho, int tv_inner, double tau,
                      const float* f, float* u, float* d_out, void* ws, hipStream_t s);
+hipError_t launch_tv_shape(const cspnp_plan& pl, int shape, double lambda, double rho, int tv_inner,
+                           double tau, const float* f, float* u, float* d_out, void* ws, hipStream_t s);
+int tv_num_shapes();
+TvShapeInfo tv_shape_info(int i);
+int tv_default_shape(int H, int W, int NR, int tv_inner);
+int xu_num_blocks();
+void xu_block_info(int i, int* bx, int* by);
 
 }  // namespace cspnp

@@ -188,6 +188,8 @@ CSPNP_API int cspnp_plan_create(const cspnp_desc* desc, const uint8_t* masks, in
   plan->desc = *desc;
   plan->device = dev;
   plan->Wq = Wq;
+  plan->tv_shape = tv_default_shape(H, W, desc->N * R, 10);
+  plan->xu_block = 0;
   CSPNP_HIP(hipMalloc(&plan->bits, packed.size() * sizeof(uint32_t)));
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   CSPNP_HIP(hipMemcpyAsync(plan->bits, packed.data(), packed.size() * sizeof(uint32_t),

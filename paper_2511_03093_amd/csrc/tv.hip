@@ -194,11 +194,6 @@ __global__ __launch_bounds__(64 * NW) void tv_kernel(const TvLaunch a) {
   }
 }
 
-struct TvShape {
-  int cx, s, nw;
-};
-constexpr TvShape kDefaultShape{2, 16, 8};
-
 template <int CX, int S, int NW>
 hipError_t launch_shape(const TvLaunch& base_args, int NR, hipStream_t st) {
   TvLaunch a = base_args;
@@ -213,13 +208,20 @@ hipError_t launch_shape(const TvLaunch& base_args, int NR, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_pass(const TvShape& sh, const TvLaunch& a, int NR, hipStream_t st) {
-  if (sh.cx == 2 && sh.s == 16 && sh.nw == 8) return launch_shape<2, 16, 8>(a, NR, st);
-  if (sh.cx == 2 && sh.s == 8 && sh.nw == 16) return launch_shape<2, 8, 16>(a, NR, st);
-  if (sh.cx == 2 && sh.s == 8 && sh.nw == 8) return launch_shape<2, 8, 8>(a, NR, st);
-  if (sh.cx == 1 && sh.s == 16 && sh.nw == 8) return launch_shape<1, 16, 8>(a, NR, st);
-  return hipErrorInvalidValue;
-}
+// Tile shapes: lane columns CX, rows per lane S, waves NW -> (64 CX) x (NW S) pixels.
+struct ShapeEntry {
+  TvShapeInfo info;
+  hipError_t (*launch)(const TvLaunch&, int, hipStream_t);
+};
+#define CSPNP_TV_SHAPE(CX, S, NW) {{CX, S, NW, 64 * CX, NW * S}, &launch_shape<CX, S, NW>}
+const ShapeEntry kShapes[] = {
+    CSPNP_TV_SHAPE(2, 16, 8),  CSPNP_TV_SHAPE(2, 16, 12), CSPNP_TV_SHAPE(2, 8, 16),
+    CSPNP_TV_SHAPE(2, 12, 16), CSPNP_TV_SHAPE(3, 8, 16),  CSPNP_TV_SHAPE(3, 12, 8), 
+    CSPNP_TV_SHAPE(3, 16, 8),  CSPNP_TV_SHAPE(1, 16, 8),  CSPNP_TV_SHAPE(2, 8, 8),
+    CSPNP_TV_SHAPE(1, 8, 8),
+};
+#undef CSPNP_TV_SHAPE
+constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
 int passes_for(int tv_inner) { return tv_inner <= kMaxFused ? 1 : (tv_inner + kMaxFused - 1) / kMaxFused; }
 
@@ -231,8 +233,33 @@ size_t tv_workspace_bytes(const cspnp_plan& pl, int tv_inner) {
   return 4 * vol * sizeof(float);  // two (px, py) buffers, ping-pong
 }
 
+int tv_num_shapes() { return kNumShapes; }
+
+TvShapeInfo tv_shape_info(int i) { return kShapes[i].info; }
+
+int tv_default_shape(int H, int W, int NR, int tv_inner) {
+  // fewest tile-pixels per launch, then the larger block (better latency hiding)
+  const int halo = tv_inner <= kMaxFused ? tv_inner : kMaxFused + 1;
+  long best = -1;
+  int bi = 0;
+  for (int i = 0; i < kNumShapes; ++i) {
+    const auto& s = kShapes[i].info;
+    const int ix = s.cols - 2 * halo, iy = s.rows - 2 * halo;
+    if (ix < 8 || iy < 8) continue;
+    const long tiles = (long)((W + ix - 1) / ix) * ((H + iy - 1) / iy) * NR;
+    const long work = tiles * s.cols * s.rows;
+    if (best < 0 || work < best) { best = work; bi = i; }
+  }
+  return bi;
+}
+
 hipError_t launch_tv(const cspnp_plan& pl, double lambda, double rho, int tv_inner, double tau,
                      const float* f, float* u, float* d_out, void* ws, hipStream_t st) {
+  return launch_tv_shape(pl, pl.tv_shape, lambda, rho, tv_inner, tau, f, u, d_out, ws, st);
+}
+
+hipError_t launch_tv_shape(const cspnp_plan& pl, int shape, double lambda, double rho, int tv_inner,
+                           double tau, const float* f, float* u, float* d_out, void* ws, hipStream_t st) {
   const auto& de = pl.desc;
   const int NR = de.N * de.R;
   TvLaunch a{};
@@ -246,7 +273,8 @@ hipError_t launch_tv(const cspnp_plan& pl, double lambda, double rho, int tv_inn
   a.theta = (float)theta;
   a.inv_theta = theta > 0 ? (float)(1.0 / theta) : 0.f;
   a.tau = (float)tau;
-  const TvShape sh = kDefaultShape;
+  if (shape < 0 || shape >= kNumShapes) return hipErrorInvalidValue;
+  const ShapeEntry& sh = kShapes[shape];
   if (theta == 0.0) tv_inner = 0;  // prox of a zero weight is the identity
   const int passes = passes_for(tv_inner);
   float* bufs[2] = {static_cast<float*>(ws), static_cast<float*>(ws) + 2 * a.vol};
@@ -258,7 +286,7 @@ hipError_t launch_tv(const cspnp_plan& pl, double lambda, double rho, int tv_inn
     a.p_in = ps == 0 ? nullptr : bufs[(ps - 1) & 1];
     a.p_out = last ? nullptr : bufs[ps & 1];
     a.halo = k + ((last && a.p_in) ? 1 : 0);
-    hipError_t e = launch_pass(sh, a, NR, st);
+    hipError_t e = sh.launch(a, NR, st);
     if (e != hipSuccess) return e;
     done += k;
   }

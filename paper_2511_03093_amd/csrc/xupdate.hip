@@ -18,8 +18,10 @@ namespace cspnp {
 
 namespace {
 
-constexpr int kXuBlockX = 64;
-constexpr int kXuBlockY = 4;
+// block shapes (threads along W, rows) selectable per plan
+constexpr int kXuShapes[][2] = {{64, 4}, {64, 8}, {128, 2}, {256, 1}, {64, 2}, {64, 1}};
+constexpr int kNumXuShapes = sizeof(kXuShapes) / sizeof(kXuShapes[0]);
+constexpr int kXuMaxThreads = 512;
 
 template <int R>
 __device__ __forceinline__ void tsolve(const ZSolve& z, double (&v)[R]) {
@@ -76,12 +78,12 @@ __device__ __forceinline__ uint32_t load_bits(const uint32_t* __restrict__ bits,
 }
 
 template <int R>
-__global__ __launch_bounds__(kXuBlockX* kXuBlockY) void xupdate_kernel(
+__global__ __launch_bounds__(kXuMaxThreads) void xupdate_kernel(
     const ZSolve z, const uint32_t* __restrict__ bits, int H, int W, int Wq,
     const float* __restrict__ y, const float* __restrict__ u, const float* __restrict__ d,
     float* __restrict__ x_out, float* __restrict__ f_out) {
-  const int w = blockIdx.x * kXuBlockX + threadIdx.x;
-  const int h = blockIdx.y * kXuBlockY + threadIdx.y;
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  const int h = blockIdx.y * blockDim.y + threadIdx.y;
   if (w >= W || h >= H) return;
   const size_t HW = (size_t)H * W;
   const size_t p = (size_t)h * W + w;
@@ -110,12 +112,12 @@ __global__ __launch_bounds__(kXuBlockX* kXuBlockY) void xupdate_kernel(
 // x-step fused with the Tikhonov u-step and the d-step (in place on u, d):
 //   f = x + d,  u = rho f / (2 lambda + rho),  d = f - u.
 template <int R>
-__global__ __launch_bounds__(kXuBlockX* kXuBlockY) void xupdate_tikhonov_kernel(
+__global__ __launch_bounds__(kXuMaxThreads) void xupdate_tikhonov_kernel(
     const ZSolve z, double shrink, const uint32_t* __restrict__ bits, int H, int W, int Wq,
     const float* __restrict__ y, float* __restrict__ u, float* __restrict__ d,
     float* __restrict__ x_out) {
-  const int w = blockIdx.x * kXuBlockX + threadIdx.x;
-  const int h = blockIdx.y * kXuBlockY + threadIdx.y;
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  const int h = blockIdx.y * blockDim.y + threadIdx.y;
   if (w >= W || h >= H) return;
   const size_t HW = (size_t)H * W;
   const size_t p = (size_t)h * W + w;
@@ -156,8 +158,9 @@ template <int R>
 hipError_t launch_r(const cspnp_plan& pl, const ZSolve& zs, const float* y, const float* u,
                     const float* d, float* x_out, float* f_out, hipStream_t s) {
   const auto& de = pl.desc;
-  dim3 block(kXuBlockX, kXuBlockY);
-  dim3 grid((de.W + kXuBlockX - 1) / kXuBlockX, (de.H + kXuBlockY - 1) / kXuBlockY);
+  const int bx = kXuShapes[pl.xu_block][0], by = kXuShapes[pl.xu_block][1];
+  dim3 block(bx, by);
+  dim3 grid((de.W + bx - 1) / bx, (de.H + by - 1) / by);
   hipLaunchKernelGGL(xupdate_kernel<R>, grid, block, 0, s, zs, pl.bits, de.H, de.W, pl.Wq, y, u, d,
                      x_out, f_out);
   return hipGetLastError();
@@ -167,8 +170,9 @@ template <int R>
 hipError_t launch_tik_r(const cspnp_plan& pl, const ZSolve& zs, double shrink, const float* y,
                         float* u, float* d, float* x_out, hipStream_t s) {
   const auto& de = pl.desc;
-  dim3 block(kXuBlockX, kXuBlockY);
-  dim3 grid((de.W + kXuBlockX - 1) / kXuBlockX, (de.H + kXuBlockY - 1) / kXuBlockY);
+  const int bx = kXuShapes[pl.xu_block][0], by = kXuShapes[pl.xu_block][1];
+  dim3 block(bx, by);
+  dim3 grid((de.W + bx - 1) / bx, (de.H + by - 1) / by);
   hipLaunchKernelGGL(xupdate_tikhonov_kernel<R>, grid, block, 0, s, zs, shrink, pl.bits, de.H, de.W,
                      pl.Wq, y, u, d, x_out);
   return hipGetLastError();
@@ -187,6 +191,13 @@ using AllR = RTable<1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 1
                     24, 25, 26, 27, 28, 29, 30, 31, 32>;
 
 }  // namespace
+
+int xu_num_blocks() { return kNumXuShapes; }
+
+void xu_block_info(int i, int* bx, int* by) {
+  *bx = kXuShapes[i][0];
+  *by = kXuShapes[i][1];
+}
 
 hipError_t launch_xupdate(const cspnp_plan& pl, const ZSolve& zs, const float* y, const float* u,
                           const float* d, float* x_out, float* f_out, hipStream_t s) {
