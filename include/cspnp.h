@@ -161,6 +161,32 @@ int cspnp_denoise(const cspnp_plan* plan, const cspnp_params* params, const floa
 int cspnp_solve(const cspnp_plan* plan, const cspnp_params* params, const float* y, float* u,
                 float* d, float* x, void* ws, void* stream);
 
+/* ---- differentiable solve (reverse mode through the unrolled iterations) --
+ * Gradients of <x_bar, x^K>, x^K the last x-step of params->iters iterations
+ * started from u = d = 0, with respect to the frames y and the scalars
+ * rho, lambda, gamma.  (The paper defines no gradient: this differentiates the
+ * iteration this library runs.)  TV (tv_inner <= 16) and Tikhonov denoisers. */
+
+/* Bytes of the checkpoint buffer: ceil(iters/ckpt_every) x (u, d) volumes. */
+int cspnp_ckpt_size(const cspnp_plan* plan, const cspnp_params* params, int ckpt_every, size_t* bytes);
+/* Device workspace bytes of cspnp_solve_bwd (256-byte aligned by the caller). */
+int cspnp_bwd_workspace_size(const cspnp_plan* plan, const cspnp_params* params, int ckpt_every,
+                             size_t* bytes);
+/* cspnp_solve from the caller's (u, d) (zero for the differentiable start),
+ * storing (u, d) at iterations 0, ckpt_every, 2 ckpt_every, ... into ckpt
+ * (float[ceil(iters/ckpt_every)][2][N*R][H][W], device).  ws as for cspnp_solve.
+ * Launches kernels directly (no graph capture). */
+int cspnp_solve_ckpt(const cspnp_plan* plan, const cspnp_params* params, const float* y, float* u,
+                     float* d, float* x, int ckpt_every, float* ckpt, void* ws, void* stream);
+/* Reverse pass: recomputes each segment from ckpt (as written by
+ * cspnp_solve_ckpt with the same params and y) and accumulates
+ *   y_bar (float[N][H][W], overwritten)  and
+ *   param_bar (device double[3], overwritten) = d<x_bar,x^K>/d(rho, lambda, gamma).
+ * x_bar: volume (read).  Deterministic (fixed-order FP64 reductions). */
+int cspnp_solve_bwd(const cspnp_plan* plan, const cspnp_params* params, const float* y, int ckpt_every,
+                    const float* ckpt, const float* x_bar, float* y_bar, double* param_bar, void* ws,
+                    void* stream);
+
 /* ---- launch-shape tuning ------------------------------------------------ */
 
 /* A plan's launch shapes: an index into the TV tile-shape table and into the

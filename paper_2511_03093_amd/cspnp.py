@@ -64,6 +64,11 @@ _SIGNATURES = {
     "cspnp_plan_get_tuning": ([_P, ctypes.POINTER(Tuning)], ctypes.c_int),
     "cspnp_plan_set_tuning": ([_P, ctypes.POINTER(Tuning)], ctypes.c_int),
     "cspnp_autotune": ([_P, ctypes.POINTER(Params), ctypes.c_char_p, ctypes.c_int, _P], ctypes.c_int),
+    "cspnp_ckpt_size": ([_P, ctypes.POINTER(Params), ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "cspnp_bwd_workspace_size": ([_P, ctypes.POINTER(Params), ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)],
+                                 ctypes.c_int),
+    "cspnp_solve_ckpt": ([_P, ctypes.POINTER(Params), _P, _P, _P, _P, ctypes.c_int, _P, _P, _P], ctypes.c_int),
+    "cspnp_solve_bwd": ([_P, ctypes.POINTER(Params), _P, ctypes.c_int, _P, _P, _P, _P, _P, _P], ctypes.c_int),
 }
 
 _lib = None
@@ -209,6 +214,28 @@ def cspnp_plan_set_tuning(plan, tv_shape, xu_block):
 def cspnp_autotune(plan, params, cache_path, force, stream):
     cp = cache_path.encode() if cache_path else None
     _call("cspnp_autotune", plan, ctypes.byref(params), cp, int(force), _P(stream))
+
+
+def cspnp_ckpt_size(plan, params, ckpt_every):
+    n = ctypes.c_size_t()
+    _call("cspnp_ckpt_size", plan, ctypes.byref(params), int(ckpt_every), ctypes.byref(n))
+    return n.value
+
+
+def cspnp_bwd_workspace_size(plan, params, ckpt_every):
+    n = ctypes.c_size_t()
+    _call("cspnp_bwd_workspace_size", plan, ctypes.byref(params), int(ckpt_every), ctypes.byref(n))
+    return n.value
+
+
+def cspnp_solve_ckpt(plan, params, y, u, d, x, ckpt_every, ckpt, ws, stream):
+    _call("cspnp_solve_ckpt", plan, ctypes.byref(params), _P(y), _P(u), _P(d), _P(x), int(ckpt_every), _P(ckpt),
+          _P(ws), _P(stream))
+
+
+def cspnp_solve_bwd(plan, params, y, ckpt_every, ckpt, x_bar, y_bar, param_bar, ws, stream):
+    _call("cspnp_solve_bwd", plan, ctypes.byref(params), _P(y), int(ckpt_every), _P(ckpt), _P(x_bar), _P(y_bar),
+          _P(param_bar), _P(ws), _P(stream))
 
 
 # --- torch-tensor convenience layer -----------------------------------------

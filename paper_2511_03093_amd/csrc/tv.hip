@@ -81,7 +81,7 @@ __global__ __launch_bounds__(64 * NW) void tv_kernel(const TvLaunch a) {
       const int gc = c0 + c;
       const bool in = rin && gc >= 0 && gc < a.W;
       const size_t off = (size_t)gr * a.W + gc;
-      fs[s][c] = in ? fn[off] * a.inv_theta : 0.f;
+      fs[s][c] = in ? __fmul_rn(fn[off], a.inv_theta) : 0.f;
       if (a.p_in) {
         px[s][c] = in ? a.p_in[base + off] : 0.f;
         py[s][c] = in ? a.p_in[a.vol + base + off] : 0.f;
