@@ -187,6 +187,40 @@ int cspnp_solve_bwd(const cspnp_plan* plan, const cspnp_params* params, const fl
                     const float* ckpt, const float* x_bar, float* y_bar, double* param_bar, void* ws,
                     void* stream);
 
+/* ---- batched solves ------------------------------------------------------
+ * Many independent snapshots (each its own shape H x W x R, N = 1, masks and
+ * parameters; TV denoiser) reconstructed by one graph of persistent grouped
+ * launches: per ADMM iteration one x-update launch per distinct R and one TV
+ * launch over all (problem, slice, tile).  Results equal the per-problem
+ * cspnp_solve bit for bit. */
+typedef struct cspnp_batch cspnp_batch;
+
+/* n problems; descs[i] as for cspnp_plan_create (denoiser must be TV);
+ * masks[i]: host uint8[R_i][H_i][W_i] in {0,1}.  Synchronous. */
+int cspnp_batch_create(int32_t n, const cspnp_desc* descs, const uint8_t* const* masks, void* stream,
+                       cspnp_batch** out);
+int cspnp_batch_destroy(cspnp_batch* batch);
+/* Device workspace bytes of cspnp_batch_solve (one f volume per problem). */
+int cspnp_batch_workspace_size(const cspnp_batch* batch, size_t* bytes);
+/* params[i] per problem (all with the same iters; tv_inner <= 16); y, u, d, x:
+ * host arrays of n device pointers with the per-problem layouts of
+ * cspnp_solve (u, d in/out, x out).  ws: 256-byte aligned workspace.  The
+ * first call for a given (params, pointers, ws) uploads the problem tables
+ * (synchronising the stream once) and captures the graph; later identical
+ * calls replay it.  Flag CSPNP_FLAG_NO_GRAPH (params[0].flags) launches
+ * directly. */
+int cspnp_batch_solve(cspnp_batch* batch, const cspnp_params* params, const float* const* y, float* const* u,
+                      float* const* d, float* const* x, void* ws, void* stream);
+/* TV tile shape (index into the same table as cspnp_tv_shape_info) of the
+ * grouped TV launch. */
+int cspnp_batch_set_tv_shape(cspnp_batch* batch, int32_t shape);
+int cspnp_batch_get_tv_shape(const cspnp_batch* batch, int32_t* shape);
+/* Time every TV tile shape on the grouped launch (HIP events on `stream`,
+ * synchronous) and keep the fastest.  Uses the given buffers as scratch:
+ * u, d and ws are overwritten. */
+int cspnp_batch_autotune(cspnp_batch* batch, const cspnp_params* params, const float* const* y,
+                         float* const* u, float* const* d, float* const* x, void* ws, void* stream);
+
 /* ---- launch-shape tuning ------------------------------------------------ */
 
 /* A plan's launch shapes: an index into the TV tile-shape table and into the

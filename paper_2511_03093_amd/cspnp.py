@@ -69,6 +69,16 @@ _SIGNATURES = {
                                  ctypes.c_int),
     "cspnp_solve_ckpt": ([_P, ctypes.POINTER(Params), _P, _P, _P, _P, ctypes.c_int, _P, _P, _P], ctypes.c_int),
     "cspnp_solve_bwd": ([_P, ctypes.POINTER(Params), _P, ctypes.c_int, _P, _P, _P, _P, _P, _P], ctypes.c_int),
+    "cspnp_batch_create": ([ctypes.c_int32, ctypes.POINTER(Desc), ctypes.POINTER(_P), _P, ctypes.POINTER(_P)],
+                           ctypes.c_int),
+    "cspnp_batch_destroy": ([_P], ctypes.c_int),
+    "cspnp_batch_workspace_size": ([_P, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "cspnp_batch_solve": ([_P, ctypes.POINTER(Params), ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
+                           ctypes.POINTER(_P), _P, _P], ctypes.c_int),
+    "cspnp_batch_set_tv_shape": ([_P, ctypes.c_int32], ctypes.c_int),
+    "cspnp_batch_get_tv_shape": ([_P, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "cspnp_batch_autotune": ([_P, ctypes.POINTER(Params), ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
+                              ctypes.POINTER(_P), _P, _P], ctypes.c_int),
 }
 
 _lib = None
@@ -238,6 +248,49 @@ def cspnp_solve_bwd(plan, params, y, ckpt_every, ckpt, x_bar, y_bar, param_bar, 
           _P(param_bar), _P(ws), _P(stream))
 
 
+def _ptr_array(ptrs):
+    return (_P * len(ptrs))(*[_P(p) for p in ptrs])
+
+
+def cspnp_batch_create(descs, mask_ptrs, stream):
+    out = _P()
+    arr = (Desc * len(descs))(*descs)
+    _call("cspnp_batch_create", len(descs), arr, _ptr_array(mask_ptrs), _P(stream), ctypes.byref(out))
+    return out
+
+
+def cspnp_batch_destroy(batch):
+    _call("cspnp_batch_destroy", batch)
+
+
+def cspnp_batch_workspace_size(batch):
+    n = ctypes.c_size_t()
+    _call("cspnp_batch_workspace_size", batch, ctypes.byref(n))
+    return n.value
+
+
+def cspnp_batch_solve(batch, params_list, y, u, d, x, ws, stream):
+    arr = (Params * len(params_list))(*params_list)
+    _call("cspnp_batch_solve", batch, arr, _ptr_array(y), _ptr_array(u), _ptr_array(d), _ptr_array(x), _P(ws),
+          _P(stream))
+
+
+def cspnp_batch_set_tv_shape(batch, shape):
+    _call("cspnp_batch_set_tv_shape", batch, int(shape))
+
+
+def cspnp_batch_get_tv_shape(batch):
+    s = ctypes.c_int32()
+    _call("cspnp_batch_get_tv_shape", batch, ctypes.byref(s))
+    return s.value
+
+
+def cspnp_batch_autotune(batch, params_list, y, u, d, x, ws, stream):
+    arr = (Params * len(params_list))(*params_list)
+    _call("cspnp_batch_autotune", batch, arr, _ptr_array(y), _ptr_array(u), _ptr_array(d), _ptr_array(x), _P(ws),
+          _P(stream))
+
+
 # --- torch-tensor convenience layer -----------------------------------------
 
 def _torch():
@@ -365,3 +418,56 @@ class Plan:
         cspnp_solve(self._handle, params, _ptr(y, "y", self.frame_shape), _ptr(u, "u", self.vol_shape),
                     _ptr(d, "d", self.vol_shape), _ptr(x, "x", self.vol_shape), self._ws_ptr(ws), _stream())
         return x, u, d
+
+
+class Batch:
+    """Many independent snapshots solved by one graph of grouped launches."""
+
+    def __init__(self, masks_list, zbc="periodic"):
+        import numpy as np
+        self._masks = [np.ascontiguousarray(m, dtype=np.uint8) for m in masks_list]
+        self.shapes = [m.shape for m in self._masks]  # (R, H, W)
+        descs = [Desc(H, W, R, 1, ZBC[zbc], DENOISER["tv"]) for (R, H, W) in self.shapes]
+        self._handle = None
+        self._handle = cspnp_batch_create(descs, [m.ctypes.data for m in self._masks], _stream())
+        self._ws = None
+
+    def close(self):
+        if self._handle is not None:
+            cspnp_batch_destroy(self._handle)
+            self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace(self):
+        torch = _torch()
+        if self._ws is None:
+            n = cspnp_batch_workspace_size(self._handle)
+            self._ws = torch.empty(n + 256, dtype=torch.uint8, device="cuda")
+        return Plan._ws_ptr(self._ws)
+
+    def allocate(self):
+        """Zeroed u, d and empty x per problem."""
+        torch = _torch()
+        u = [torch.zeros(s, dtype=torch.float32, device="cuda") for s in self.shapes]
+        d = [torch.zeros(s, dtype=torch.float32, device="cuda") for s in self.shapes]
+        x = [torch.empty(s, dtype=torch.float32, device="cuda") for s in self.shapes]
+        return u, d, x
+
+    def solve(self, params_list, y, u, d, x):
+        for i, (R, H, W) in enumerate(self.shapes):
+            _ptr(y[i], "y[i]", (1, H, W))
+            for t, nm in ((u[i], "u[i]"), (d[i], "d[i]"), (x[i], "x[i]")):
+                _ptr(t, nm, (R, H, W))
+        cspnp_batch_solve(self._handle, params_list, [t.data_ptr() for t in y], [t.data_ptr() for t in u],
+                          [t.data_ptr() for t in d], [t.data_ptr() for t in x], self.workspace(), _stream())
+        return x, u, d
+
+    def autotune(self, params_list, y, u, d, x):
+        cspnp_batch_autotune(self._handle, params_list, [t.data_ptr() for t in y], [t.data_ptr() for t in u],
+                             [t.data_ptr() for t in d], [t.data_ptr() for t in x], self.workspace(), _stream())
+        return cspnp_batch_get_tv_shape(self._handle)

@@ -20,7 +20,7 @@
 #include <algorithm>
 #include <vector>
 
-#include "common.hpp"
+#include "xupdate_impl.hpp"
 
 namespace cspnp {
 ZSolve make_zsolve(int R, int zbc, double rho, double gamma);
@@ -211,46 +211,6 @@ __global__ __launch_bounds__(kThreads) void tikb(size_t n, const float* __restri
 }
 
 template <int R>
-__device__ __forceinline__ void tsolve_b(const ZSolve& z, double (&v)[R]) {
-#pragma unroll
-  for (int i = 1; i < R; ++i) v[i] = fma(-z.l[i], v[i - 1], v[i]);
-  v[R - 1] *= z.invd[R - 1];
-#pragma unroll
-  for (int i = R - 2; i >= 0; --i) v[i] = fma(-z.l[i + 1], v[i + 1], v[i] * z.invd[i]);
-}
-
-// lam = A^{-1} a (same factorisation as the forward x-step)
-template <int R>
-__device__ __forceinline__ void apply_ainv(const ZSolve& z, uint32_t m, double (&a)[R]) {
-  double b[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) b[r] = (double)((m >> r) & 1u);
-  tsolve_b<R>(z, a);
-  tsolve_b<R>(z, b);
-  double mTa = 0.0, mTb = 0.0;
-#pragma unroll
-  for (int r = 0; r < R; ++r)
-    if ((m >> r) & 1u) {
-      mTa += a[r];
-      mTb += b[r];
-    }
-  if (z.periodic) {
-    const double gm = z.gamma;
-    const double wTa = a[0] - a[R - 1], wTb = b[0] - b[R - 1];
-    const double c11 = 1.0 + mTb, c12 = wTb, c21 = gm * wTb, c22 = 1.0 + gm * z.wc;
-    const double inv = 1.0 / (c11 * c22 - c12 * c21);
-    const double alpha = (mTa * c22 - c12 * gm * wTa) * inv;
-    const double beta = (c11 * gm * wTa - c21 * mTa) * inv;
-#pragma unroll
-    for (int r = 0; r < R; ++r) a[r] = a[r] - alpha * b[r] - beta * z.c[r];
-  } else {
-    const double alpha = mTa / (1.0 + mTb);
-#pragma unroll
-    for (int r = 0; r < R; ++r) a[r] = fma(-alpha, b[r], a[r]);
-  }
-}
-
-template <int R>
 __global__ __launch_bounds__(kThreads) void xupdate_bwd(const ZSolve z, int periodic_lap, const uint32_t* __restrict__ bits,
                                                         int H, int W, int Wq, const float* __restrict__ fbar,
                                                         const float* __restrict__ xbar, const float* __restrict__ uk,
@@ -273,7 +233,7 @@ __global__ __launch_bounds__(kThreads) void xupdate_bwd(const ZSolve z, int peri
       lam[r] = (double)fb[r] + (xbar ? (double)xbar[r * HW + p] : 0.0);
       xv[r] = (double)fk[r * HW + p] - (double)dk[r * HW + p];
     }
-    apply_ainv<R>(z, m, lam);
+    xuimpl::pixel_solve<R>(z, m, lam);
     double yb = 0.0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {

@@ -12,70 +12,19 @@
 // exactly the paper's element-wise update (end of Sec. III-B).
 // One thread per pixel, the z-vector in FP64 registers, FP32 in/out; the
 // kernel streams u, d (8 B/voxel) and writes f = x + d (4 B/voxel): HBM-bound.
-#include "common.hpp"
+#include "xupdate_impl.hpp"
 
 namespace cspnp {
 
 namespace {
 
+using xuimpl::load_bits;
+using xuimpl::pixel_solve;
+
 // block shapes (threads along W, rows) selectable per plan
 constexpr int kXuShapes[][2] = {{64, 4}, {64, 8}, {128, 2}, {256, 1}, {64, 2}, {64, 1}};
 constexpr int kNumXuShapes = sizeof(kXuShapes) / sizeof(kXuShapes[0]);
 constexpr int kXuMaxThreads = 512;
-
-template <int R>
-__device__ __forceinline__ void tsolve(const ZSolve& z, double (&v)[R]) {
-  // L z = v, then z *= D^{-1}, then L^T x = z
-#pragma unroll
-  for (int i = 1; i < R; ++i) v[i] = fma(-z.l[i], v[i - 1], v[i]);
-  v[R - 1] *= z.invd[R - 1];
-#pragma unroll
-  for (int i = R - 2; i >= 0; --i) v[i] = fma(-z.l[i + 1], v[i + 1], v[i] * z.invd[i]);
-}
-
-// Solves the pixel system; on return a[] holds x.
-template <int R>
-__device__ __forceinline__ void pixel_solve(const ZSolve& z, uint32_t m, double (&a)[R]) {
-  double b[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) b[r] = (double)((m >> r) & 1u);
-  tsolve<R>(z, a);
-  tsolve<R>(z, b);
-  double mTa = 0.0, mTb = 0.0;
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    if ((m >> r) & 1u) {
-      mTa += a[r];
-      mTb += b[r];
-    }
-  }
-  if (z.periodic) {
-    const double g = z.gamma;
-    const double wTa = a[0] - a[R - 1];
-    const double wTb = b[0] - b[R - 1];
-    // [1 + mTb, wTb; g wTb, 1 + g wc] [alpha; beta'] = [mTa; g wTa], beta' = sqrt(g) beta
-    const double c11 = 1.0 + mTb, c12 = wTb, c21 = g * wTb, c22 = 1.0 + g * z.wc;
-    const double r1 = mTa, r2 = g * wTa;
-    const double inv = 1.0 / (c11 * c22 - c12 * c21);
-    const double alpha = (r1 * c22 - c12 * r2) * inv;
-    const double beta = (c11 * r2 - c21 * r1) * inv;
-#pragma unroll
-    for (int r = 0; r < R; ++r) a[r] = a[r] - alpha * b[r] - beta * z.c[r];
-  } else {
-    const double alpha = mTa / (1.0 + mTb);
-#pragma unroll
-    for (int r = 0; r < R; ++r) a[r] = fma(-alpha, b[r], a[r]);
-  }
-}
-
-template <int R>
-__device__ __forceinline__ uint32_t load_bits(const uint32_t* __restrict__ bits, int H, int Wq,
-                                              int h, int w) {
-  uint32_t m = 0;
-#pragma unroll
-  for (int r = 0; r < R; ++r) m |= ((bits[((size_t)r * H + h) * Wq + (w >> 5)] >> (w & 31)) & 1u) << r;
-  return m;
-}
 
 template <int R>
 __global__ __launch_bounds__(kXuMaxThreads) void xupdate_kernel(
