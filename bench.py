@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=8, help="oracle iterations in the CPU sample")
     ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched (64 snapshots) and differentiable (fwd+bwd) measurements")
+    ap.add_argument("--extra-steps", type=int, default=3)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (HBM counter calibration)")
     return ap.parse_args()
@@ -74,6 +77,98 @@ def cpu_baseline(prob, p, iters):
     return {"value": nvox * iters / dt, "unit": "voxel-iters/s", "cores": 1, "kind": "oracle",
             "sample": f"{iters} ADMM iterations of the same 512x512x16 TV+temporal problem "
                       f"(FP64 NumPy, single thread): {dt:.2f} s"}
+
+
+def timed(fn, steps, warmup):
+    """Mean seconds per call of fn (HIP events on torch's current stream)."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    s = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(steps):
+        fn()
+    e.record()
+    e.synchronize()
+    return s.elapsed_time(e) / 1e3 / steps
+
+
+def batched_vs_plain(steps):
+    """64 uneven snapshots (TV + temporal, 100 iterations): one batched graph vs 64 plain solves."""
+    import torch
+
+    import synth
+    from paper_2511_03093_amd import cspnp
+    probs = [synth.make(3, snapshot=s) for s in range(64)]
+    params = [cspnp.params_from(probs[0].params)] * 64
+    iters = probs[0].params["iters"]
+    nvox = sum(int(p.gt.size) for p in probs)
+    y = [torch.from_numpy(p.y).cuda() for p in probs]
+    batch = cspnp.Batch([p.masks for p in probs])
+    u, d, x = batch.allocate()
+    shape = batch.autotune(params, y, u, d, x)
+
+    def run_batched():
+        for t in u + d:
+            t.zero_()
+        batch.solve(params, y, u, d, x)
+
+    t_b = timed(run_batched, steps, 1)
+    plans = [cspnp.Plan(p.masks, denoiser="tv") for p in probs]
+    for pl in plans:
+        pl.autotune(params[0])
+    wss = [pl.workspace(params[0]) for pl in plans]
+
+    def run_plain():
+        for i, pl in enumerate(plans):
+            u[i].zero_()
+            d[i].zero_()
+            pl.solve(params[0], y[i], u[i], d[i], x[i], wss[i])
+
+    t_p = timed(run_plain, steps, 1)
+    for pl in plans:
+        pl.close()
+    batch.close()
+    return {"workload": "64 snapshots, sizes {256^2, 512^2, 768x512, 1024^2}, B in {8,16,24}, TV + temporal 0.1, "
+                        "100 iterations", "voxels": nvox, "batched_ms": t_b * 1e3, "plain_ms": t_p * 1e3,
+            "batched_voxel_iters_per_s": nvox * iters / t_b, "plain_voxel_iters_per_s": nvox * iters / t_p,
+            "speedup": t_p / t_b, "batch_tv_tile": list(cspnp.cspnp_tv_shape_info(shape)),
+            "accuracy": "batched results equal the plain solves bit for bit (tests/test_gpu_batch.py)"}
+
+
+def fwd_bwd(steps):
+    """512x512x16 TV + temporal, 30 unrolled iterations, checkpoint every 5: forward + backward."""
+    import torch
+
+    import synth
+    from paper_2511_03093_amd import cspnp
+    from paper_2511_03093_amd.autograd import pnp_admm
+    prob = synth.make(4)
+    pd = prob.params
+    plan = cspnp.Plan(prob.masks, denoiser="tv")
+    plan.autotune(cspnp.params_from(pd))
+    y0 = torch.from_numpy(prob.y).cuda()
+    gt = torch.from_numpy(prob.gt).cuda()
+
+    def run():
+        y = y0.clone().requires_grad_(True)
+        sc = [torch.tensor(v, dtype=torch.float64, requires_grad=True) for v in (pd["rho"], pd["lam"], pd["gamma"])]
+        xk = pnp_admm(y, *sc, plan, iters=pd["iters"], tv_inner=pd["tv_inner"], ckpt_every=pd["ckpt_every"])
+        loss = torch.mean((xk - gt) ** 2)
+        loss.backward()
+
+    def fwd():
+        with torch.no_grad():
+            pnp_admm(y0, pd["rho"], pd["lam"], pd["gamma"], plan, iters=pd["iters"], tv_inner=pd["tv_inner"],
+                     ckpt_every=pd["ckpt_every"])
+
+    t_fb = timed(run, steps, 1)
+    t_f = timed(fwd, steps, 1)
+    plan.close()
+    return {"workload": "512x512x16 TV + temporal, 30 unrolled iterations, checkpoint every 5, MSE loss",
+            "fwd_bwd_ms": t_fb * 1e3, "fwd_ms": t_f * 1e3, "bwd_ms": (t_fb - t_f) * 1e3}
 
 
 def main():
@@ -187,6 +282,9 @@ def main():
         dst = torch.empty(n, device="cuda")
         t_cp = time_launches(lambda: dst.copy_(src), 5)
         out["copy_probe"] = {"MiB": a.copy_probe_mib, "us": t_cp * 1e6, "GB/s": 2 * n * 4 / t_cp / 1e9}
+    if not a.no_extras:
+        out["batched"] = batched_vs_plain(a.extra_steps)
+        out["differentiable"] = fwd_bwd(a.extra_steps)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, pd, a.cpu_iters)
     print(json.dumps(out), flush=True)
