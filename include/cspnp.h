@@ -161,6 +161,23 @@ int cspnp_denoise(const cspnp_plan* plan, const cspnp_params* params, const floa
 int cspnp_solve(const cspnp_plan* plan, const cspnp_params* params, const float* y, float* u,
                 float* d, float* x, void* ws, void* stream);
 
+/* ---- BM3D stage inspection ------------------------------------------------
+ * The BM3D u-step (plan denoiser CSPNP_DENOISER_BM3D, params->bm3d_sigma the
+ * noise level) runs inside cspnp_denoise / cspnp_solve.  These calls expose
+ * its intermediate results for verification: cspnp_bm3d_stage runs the
+ * stage-1 block matching on f (stage 0), additionally the hard-threshold
+ * stage producing the FP64 basic estimate (stage 1), or additionally the
+ * stage-2 matching on the basic estimate (stage 2), into ws (the
+ * CSPNP_WS_DENOISE workspace).  cspnp_bm3d_layout gives the byte offsets in
+ * ws of the match lists int32[N*R][nry][nrx][16] (raster index y*W + x of
+ * each block, reference first), of the group sizes int32[N*R][nry][nrx] and
+ * of the basic estimate double[N*R][H][W], and the reference-grid size
+ * (references at rows 0, 3, 6, ... and H-8; columns likewise). */
+int cspnp_bm3d_stage(const cspnp_plan* plan, const cspnp_params* params, const float* f, int stage, void* ws,
+                     void* stream);
+int cspnp_bm3d_layout(const cspnp_plan* plan, size_t* matches_offset, size_t* counts_offset,
+                      size_t* basic_offset, int32_t* nry, int32_t* nrx);
+
 /* ---- differentiable solve (reverse mode through the unrolled iterations) --
  * Gradients of <x_bar, x^K>, x^K the last x-step of params->iters iterations
  * started from u = d = 0, with respect to the frames y and the scalars

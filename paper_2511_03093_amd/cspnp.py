@@ -69,6 +69,10 @@ _SIGNATURES = {
                                  ctypes.c_int),
     "cspnp_solve_ckpt": ([_P, ctypes.POINTER(Params), _P, _P, _P, _P, ctypes.c_int, _P, _P, _P], ctypes.c_int),
     "cspnp_solve_bwd": ([_P, ctypes.POINTER(Params), _P, ctypes.c_int, _P, _P, _P, _P, _P, _P], ctypes.c_int),
+    "cspnp_bm3d_stage": ([_P, ctypes.POINTER(Params), _P, ctypes.c_int, _P, _P], ctypes.c_int),
+    "cspnp_bm3d_layout": ([_P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
+                           ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_int32),
+                           ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "cspnp_batch_create": ([ctypes.c_int32, ctypes.POINTER(Desc), ctypes.POINTER(_P), _P, ctypes.POINTER(_P)],
                            ctypes.c_int),
     "cspnp_batch_destroy": ([_P], ctypes.c_int),
@@ -246,6 +250,18 @@ def cspnp_solve_ckpt(plan, params, y, u, d, x, ckpt_every, ckpt, ws, stream):
 def cspnp_solve_bwd(plan, params, y, ckpt_every, ckpt, x_bar, y_bar, param_bar, ws, stream):
     _call("cspnp_solve_bwd", plan, ctypes.byref(params), _P(y), int(ckpt_every), _P(ckpt), _P(x_bar), _P(y_bar),
           _P(param_bar), _P(ws), _P(stream))
+
+
+def cspnp_bm3d_stage(plan, params, f, stage, ws, stream):
+    _call("cspnp_bm3d_stage", plan, ctypes.byref(params), _P(f), int(stage), _P(ws), _P(stream))
+
+
+def cspnp_bm3d_layout(plan):
+    a, b, c = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    ny, nx = ctypes.c_int32(), ctypes.c_int32()
+    _call("cspnp_bm3d_layout", plan, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(ny),
+          ctypes.byref(nx))
+    return dict(matches=a.value, counts=b.value, basic=c.value, nry=ny.value, nrx=nx.value)
 
 
 def _ptr_array(ptrs):

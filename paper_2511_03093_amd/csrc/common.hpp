@@ -78,6 +78,7 @@ struct cspnp_plan {
   cspnp::GraphCache graph;
   int tv_shape = 0;  // index into the TV tile-shape table
   int xu_block = 0;  // index into the x-update block-shape table
+  double* dct = nullptr;  // device 8x8 DCT-II matrix (BM3D plans)
   ~cspnp_plan();
 };
 
@@ -106,6 +107,10 @@ hipError_t launch_tv(const cspnp_plan& pl, double lambda, double rho, int tv_inn
                      const float* f, float* u, float* d_out, void* ws, hipStream_t s);
 hipError_t launch_tv_shape(const cspnp_plan& pl, int shape, double lambda, double rho, int tv_inner,
                            double tau, const float* f, float* u, float* d_out, void* ws, hipStream_t s);
+size_t bm3d_workspace_bytes(const cspnp_plan& pl);
+void make_dct_matrix(double* c);  // 64 entries, row k = frequency
+hipError_t launch_bm3d(const cspnp_plan& pl, double sigma, const float* f, float* u, float* d_out, void* ws,
+                       hipStream_t s);
 int tv_num_shapes();
 TvShapeInfo tv_shape_info(int i);
 int tv_default_shape(int H, int W, int NR, int tv_inner);

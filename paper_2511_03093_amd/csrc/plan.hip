@@ -43,6 +43,8 @@ static int validate_desc(const cspnp_desc* d) {
   if (d->denoiser != CSPNP_DENOISER_TIKHONOV && d->denoiser != CSPNP_DENOISER_TV &&
       d->denoiser != CSPNP_DENOISER_BM3D)
     return fail(CSPNP_EINVAL, "unknown denoiser");
+  if (d->denoiser == CSPNP_DENOISER_BM3D && (d->H < 8 || d->W < 8))
+    return fail(CSPNP_EINVAL, "the BM3D denoiser needs H, W >= 8 (8x8 blocks)");
   if ((int64_t)d->H * d->W > (int64_t(1) << 30))
     return fail(CSPNP_EINVAL, "H*W must be <= 2^30");
   return CSPNP_OK;
@@ -129,6 +131,7 @@ cspnp_plan::~cspnp_plan() {
   if (graph.graph) (void)hipGraphDestroy(graph.graph);
   if (capture_stream) (void)hipStreamDestroy(capture_stream);
   if (bits) (void)hipFree(bits);
+  if (dct) (void)hipFree(dct);
 }
 
 CSPNP_API int cspnp_version(void) { return CSPNP_VERSION; }
@@ -194,6 +197,12 @@ CSPNP_API int cspnp_plan_create(const cspnp_desc* desc, const uint8_t* masks, in
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   CSPNP_HIP(hipMemcpyAsync(plan->bits, packed.data(), packed.size() * sizeof(uint32_t),
                            hipMemcpyHostToDevice, st));
+  if (desc->denoiser == CSPNP_DENOISER_BM3D) {
+    double c[64];
+    make_dct_matrix(c);
+    CSPNP_HIP(hipMalloc(&plan->dct, sizeof c));
+    CSPNP_HIP(hipMemcpyAsync(plan->dct, c, sizeof c, hipMemcpyHostToDevice, st));
+  }
   CSPNP_HIP(hipStreamSynchronize(st));
   CSPNP_HIP(hipStreamCreateWithFlags(&plan->capture_stream, hipStreamNonBlocking));
   *out = plan.release();

@@ -19,6 +19,7 @@ size_t volume_elems(const cspnp_plan& pl) { return (size_t)pl.desc.N * pl.desc.R
 
 size_t denoise_ws_bytes(const cspnp_plan& pl, const cspnp_params& p) {
   if (pl.desc.denoiser == CSPNP_DENOISER_TV) return align_up(tv_workspace_bytes(pl, p.tv_inner));
+  if (pl.desc.denoiser == CSPNP_DENOISER_BM3D) return align_up(bm3d_workspace_bytes(pl));
   return 0;
 }
 
@@ -40,6 +41,7 @@ hipError_t enqueue_denoise(const cspnp_plan& pl, const cspnp_params& p, const fl
   switch (pl.desc.denoiser) {
     case CSPNP_DENOISER_TIKHONOV: return launch_tikhonov(pl, p.lambda, p.rho, f, u, d_out, s);
     case CSPNP_DENOISER_TV: return launch_tv(pl, p.lambda, p.rho, p.tv_inner, p.tv_tau, f, u, d_out, ws, s);
+    case CSPNP_DENOISER_BM3D: return launch_bm3d(pl, p.bm3d_sigma, f, u, d_out, ws, s);
     default: return hipErrorNotSupported;
   }
 }
@@ -140,7 +142,6 @@ CSPNP_API int cspnp_denoise(const cspnp_plan* plan, const cspnp_params* params, 
   if (int s = check_ptr(u, "u")) return s;
   if (d_out && check_ptr(d_out, "d_out")) return CSPNP_EINVAL;
   if (u == f || d_out == f || (d_out && d_out == u)) return fail(CSPNP_EINVAL, "u/d_out must not alias f or each other");
-  if (plan->desc.denoiser == CSPNP_DENOISER_BM3D) return fail(CSPNP_EUNSUPPORTED, "BM3D denoiser not built");
   if (int s = check_ws(*plan, denoise_ws_bytes(*plan, *params), ws)) return s;
   CSPNP_HIP(enqueue_denoise(*plan, *params, f, u, d_out, ws, as_stream(stream)));
   return CSPNP_OK;
@@ -156,7 +157,6 @@ CSPNP_API int cspnp_solve(const cspnp_plan* cplan, const cspnp_params* params, c
   if (int s = check_ptr(d, "d")) return s;
   if (int s = check_ptr(x, "x")) return s;
   if (u == d || x == u || x == d) return fail(CSPNP_EINVAL, "u, d and x must be distinct buffers");
-  if (cplan->desc.denoiser == CSPNP_DENOISER_BM3D) return fail(CSPNP_EUNSUPPORTED, "BM3D denoiser not built");
   if (int s = check_ws(*cplan, solve_ws_bytes(*cplan, *params), ws)) return s;
   cspnp_plan* plan = const_cast<cspnp_plan*>(cplan);  // the graph cache is mutable state
   hipStream_t st = as_stream(stream);
