@@ -76,7 +76,7 @@ __global__ __launch_bounds__(kThreads) void tvb_w(Geo g, const float* __restrict
     const float pyu = h > 0 ? py[i - g.W] : 0.f;
     const float pxc = w < g.W - 1 ? px[i] : 0.f;
     const float pyc = h < g.H - 1 ? py[i] : 0.f;
-    wo[i] = (pxc - pxl) + (pyc - pyu) - __fmul_rn(f[i], inv_theta);
+    wo[i] = (((pxc - pxl) + pyc) - pyu) - __fmul_rn(f[i], inv_theta);
   }
 }
 

@@ -53,7 +53,8 @@ __device__ __forceinline__ bool next_entry(int& e, int& step, int n, bool first)
 
 template <int R>
 __global__ __launch_bounds__(kXuThreads) void batch_xupdate(const XuProblem* __restrict__ probs,
-                                                            const int2* __restrict__ entries, int n, int emit_x) {
+                                                            const int2* __restrict__ entries, int n, int emit_x,
+                                                            int d_from_f) {
   int e, step;
   for (bool ok = next_entry(e, step, n, true); ok; ok = next_entry(e, step, n, false)) {
     const int2 en = entries[e];
@@ -69,7 +70,7 @@ __global__ __launch_bounds__(kXuThreads) void batch_xupdate(const XuProblem* __r
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const float ur = P.u[(size_t)r * HW + p];
-      dv[r] = P.d[(size_t)r * HW + p];
+      dv[r] = d_from_f ? P.f[(size_t)r * HW + p] - ur : P.d[(size_t)r * HW + p];
       a[r] = P.z.rho * ((double)ur - (double)dv[r]);
       if ((m >> r) & 1u) a[r] += yv;
     }
@@ -85,27 +86,27 @@ __global__ __launch_bounds__(kXuThreads) void batch_xupdate(const XuProblem* __r
 
 template <int CX, int S, int NW>
 __global__ __launch_bounds__(64 * NW) void batch_tv(const TvLaunch* __restrict__ probs, const int4* __restrict__ entries,
-                                                    int n) {
-  __shared__ float lds_py[NW][64 * CX];
-  __shared__ float lds_w[NW][64 * CX];
+                                                    int n, int write_d) {
+  __shared__ tvimpl::TvExchange<CX, NW> xch;
   int e, step;
   for (bool ok = next_entry(e, step, n, true); ok; ok = next_entry(e, step, n, false)) {
     const int4 en = entries[e];
-    const TvLaunch a = probs[en.x];
+    TvLaunch a = probs[en.x];
+    if (!write_d) a.d_out = nullptr;
     __syncthreads();  // the previous tile's epilogue has finished reading LDS
-    tvimpl::tv_tile<CX, S, NW>(a, en.y, en.z, lds_py, lds_w);
+    tvimpl::tv_tile<CX, S, NW>(a, en.y, en.z, xch);
   }
 }
 
 struct BatchShape {
   int cx, s, nw;
   const void* kernel;
-  hipError_t (*launch)(int grid, const TvLaunch*, const int4*, int, hipStream_t);
+  hipError_t (*launch)(int grid, const TvLaunch*, const int4*, int, int, hipStream_t);
 };
 
 template <int CX, int S, int NW>
-hipError_t launch_batch_tv(int grid, const TvLaunch* p, const int4* e, int n, hipStream_t st) {
-  hipLaunchKernelGGL((batch_tv<CX, S, NW>), dim3(grid), dim3(64 * NW), 0, st, p, e, n);
+hipError_t launch_batch_tv(int grid, const TvLaunch* p, const int4* e, int n, int write_d, hipStream_t st) {
+  hipLaunchKernelGGL((batch_tv<CX, S, NW>), dim3(grid), dim3(64 * NW), 0, st, p, e, n, write_d);
   return hipGetLastError();
 }
 
@@ -282,12 +283,12 @@ int prepare(cspnp_batch& b, const cspnp_params* params, const float* const* y, f
   return CSPNP_OK;
 }
 
-hipError_t enqueue_batch_xu(cspnp_batch& b, int emit_x, hipStream_t st) {
+hipError_t enqueue_batch_xu(cspnp_batch& b, int emit_x, int d_from_f, hipStream_t st) {
   for (size_t g = 0; g < b.rvals.size(); ++g) {
     const int n = (int)b.h_xu_entries[g].size();
     hipError_t e = AllR::dispatch(b.rvals[g], [&](auto rc) {
       hipLaunchKernelGGL(batch_xupdate<decltype(rc)::value>, dim3(b.xu_grid[g]), dim3(kXuThreads), 0, st, b.d_xu.p,
-                         b.d_xu_entries[g]->p, n, emit_x);
+                         b.d_xu_entries[g]->p, n, emit_x, d_from_f);
       return hipGetLastError();
     });
     if (e != hipSuccess) return e;
@@ -295,15 +296,16 @@ hipError_t enqueue_batch_xu(cspnp_batch& b, int emit_x, hipStream_t st) {
   return hipSuccess;
 }
 
-hipError_t enqueue_batch_tv(cspnp_batch& b, hipStream_t st) {
-  return kBShapes[b.tv_shape].launch(b.tv_grid, b.d_tv.p, b.d_tv_entries.p, (int)b.h_tv_entries.size(), st);
+hipError_t enqueue_batch_tv(cspnp_batch& b, int write_d, hipStream_t st) {
+  return kBShapes[b.tv_shape].launch(b.tv_grid, b.d_tv.p, b.d_tv_entries.p, (int)b.h_tv_entries.size(), write_d, st);
 }
 
 hipError_t enqueue_batch_iters(cspnp_batch& b, int iters, hipStream_t st) {
+  // state carried as (u, f) between iterations, as in the single-problem solve
   for (int k = 0; k < iters; ++k) {
-    hipError_t e = enqueue_batch_xu(b, k == iters - 1, st);
+    hipError_t e = enqueue_batch_xu(b, k == iters - 1, k > 0, st);
     if (e != hipSuccess) return e;
-    e = enqueue_batch_tv(b, st);
+    e = enqueue_batch_tv(b, k == iters - 1, st);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -436,9 +438,9 @@ CSPNP_API int cspnp_batch_autotune(cspnp_batch* b, const cspnp_params* params, c
     b->drop_graph();
     if (prepare(*b, params, y, u, d, x, static_cast<char*>(ws), st) != CSPNP_OK) { clear_error(); continue; }
     CSPNP_HIP(hipStreamSynchronize(st));
-    CSPNP_HIP(enqueue_batch_tv(*b, st));
+    CSPNP_HIP(enqueue_batch_tv(*b, 1, st));
     CSPNP_HIP(hipEventRecord(e0, st));
-    for (int r = 0; r < 3; ++r) CSPNP_HIP(enqueue_batch_tv(*b, st));
+    for (int r = 0; r < 3; ++r) CSPNP_HIP(enqueue_batch_tv(*b, 1, st));
     CSPNP_HIP(hipEventRecord(e1, st));
     CSPNP_HIP(hipEventSynchronize(e1));
     float ms = 0.f;

@@ -93,8 +93,9 @@ hipError_t launch_forward(const cspnp_plan& pl, const float* x, float* y, hipStr
 hipError_t launch_adjoint(const cspnp_plan& pl, const float* y, float* x, hipStream_t s);
 // x-step; writes x_out and/or f_out = x + d.  When tik_lam_over >= 0 the
 // Tikhonov prox and d-step are fused: u_out = rho f/(2 lambda + rho), d_out = f - u.
+// d_from_f: `d` holds the previous f and d = f - u is formed on the fly (f_out may alias it).
 hipError_t launch_xupdate(const cspnp_plan& pl, const ZSolve& zs, const float* y, const float* u,
-                          const float* d, float* x_out, float* f_out, hipStream_t s);
+                          const float* d, float* x_out, float* f_out, hipStream_t s, bool d_from_f = false);
 hipError_t launch_xupdate_tikhonov(const cspnp_plan& pl, const ZSolve& zs, double lambda,
                                    const float* y, float* u, float* d, float* x_out,
                                    hipStream_t s);

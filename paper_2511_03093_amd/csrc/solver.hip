@@ -56,12 +56,16 @@ hipError_t enqueue_iterations(const cspnp_plan& pl, const cspnp_params& p, const
     }
     return hipSuccess;
   }
+  // Between iterations the state is carried as (u, f): the u-step writes only u, and the next
+  // x-step forms d = f - u itself (the same FP32 subtraction the u-step would store).  The
+  // caller's d is read by the first x-step and written by the last u-step.
   float* f = static_cast<float*>(ws);
   void* dws = static_cast<char*>(ws) + align_up(volume_elems(pl) * sizeof(float));
   for (int k = 0; k < p.iters; ++k) {
-    hipError_t e = launch_xupdate(pl, zs, y, u, d, k == p.iters - 1 ? x : nullptr, f, s);
+    const bool first = k == 0, last = k == p.iters - 1;
+    hipError_t e = launch_xupdate(pl, zs, y, u, first ? d : f, last ? x : nullptr, f, s, !first);
     if (e != hipSuccess) return e;
-    e = enqueue_denoise(pl, p, f, u, d, dws, s);
+    e = enqueue_denoise(pl, p, f, u, last ? d : nullptr, dws, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

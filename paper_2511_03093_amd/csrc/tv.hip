@@ -11,7 +11,8 @@
 // slice: lane L of wave k holds rows k*S..k*S+S-1 and columns L*CX..L*CX+CX-1
 // of p and f/theta in registers for all inner iterations.  Horizontal
 // neighbours come from the adjacent lane by DPP wave shifts, vertical
-// neighbours across waves through LDS (two barriers per inner iteration).
+// neighbours across waves through double-buffered LDS (one barrier per inner
+// iteration).
 // Values beyond the tile edge are not available, and the error they cause
 // spreads one pixel per iteration, so the tile carries a halo of `iters`
 // pixels (one more when p is loaded) and writes only its interior.  Pixels
@@ -31,9 +32,8 @@ constexpr int kMaxFused = 16;
 
 template <int CX, int S, int NW>
 __global__ __launch_bounds__(64 * NW) void tv_kernel(const TvLaunch a) {
-  __shared__ float lds_py[NW][64 * CX];
-  __shared__ float lds_w[NW][64 * CX];
-  tv_tile<CX, S, NW>(a, blockIdx.x, blockIdx.y, lds_py, lds_w);
+  __shared__ tvimpl::TvExchange<CX, NW> xch;
+  tv_tile<CX, S, NW>(a, blockIdx.x, blockIdx.y, xch);
 }
 
 template <int CX, int S, int NW>

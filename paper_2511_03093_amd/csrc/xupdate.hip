@@ -26,11 +26,13 @@ constexpr int kXuShapes[][2] = {{64, 4}, {64, 8}, {128, 2}, {256, 1}, {64, 2}, {
 constexpr int kNumXuShapes = sizeof(kXuShapes) / sizeof(kXuShapes[0]);
 constexpr int kXuMaxThreads = 512;
 
+// `d` is the dual variable, or (d_from_f) the previous f, with d = f - u formed
+// here exactly as the TV epilogue forms it; f_out may then alias `d`.
 template <int R>
 __global__ __launch_bounds__(kXuMaxThreads) void xupdate_kernel(
     const ZSolve z, const uint32_t* __restrict__ bits, int H, int W, int Wq,
-    const float* __restrict__ y, const float* __restrict__ u, const float* __restrict__ d,
-    float* __restrict__ x_out, float* __restrict__ f_out) {
+    const float* __restrict__ y, const float* __restrict__ u, const float* d, int d_from_f,
+    float* __restrict__ x_out, float* f_out) {
   const int w = blockIdx.x * blockDim.x + threadIdx.x;
   const int h = blockIdx.y * blockDim.y + threadIdx.y;
   if (w >= W || h >= H) return;
@@ -43,7 +45,7 @@ __global__ __launch_bounds__(kXuMaxThreads) void xupdate_kernel(
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const float ur = u[r * HW + p];
-    dv[r] = d[r * HW + p];
+    dv[r] = d_from_f ? d[r * HW + p] - ur : d[r * HW + p];
     a[r] = z.rho * ((double)ur - (double)dv[r]);
     if ((m >> r) & 1u) a[r] += yv;
   }
@@ -105,13 +107,13 @@ __global__ __launch_bounds__(256) void tikhonov_kernel(float shrink, size_t n, c
 
 template <int R>
 hipError_t launch_r(const cspnp_plan& pl, const ZSolve& zs, const float* y, const float* u,
-                    const float* d, float* x_out, float* f_out, hipStream_t s) {
+                    const float* d, int d_from_f, float* x_out, float* f_out, hipStream_t s) {
   const auto& de = pl.desc;
   const int bx = kXuShapes[pl.xu_block][0], by = kXuShapes[pl.xu_block][1];
   dim3 block(bx, by);
   dim3 grid((de.W + bx - 1) / bx, (de.H + by - 1) / by);
   hipLaunchKernelGGL(xupdate_kernel<R>, grid, block, 0, s, zs, pl.bits, de.H, de.W, pl.Wq, y, u, d,
-                     x_out, f_out);
+                     d_from_f, x_out, f_out);
   return hipGetLastError();
 }
 
@@ -149,9 +151,9 @@ void xu_block_info(int i, int* bx, int* by) {
 }
 
 hipError_t launch_xupdate(const cspnp_plan& pl, const ZSolve& zs, const float* y, const float* u,
-                          const float* d, float* x_out, float* f_out, hipStream_t s) {
+                          const float* d, float* x_out, float* f_out, hipStream_t s, bool d_from_f) {
   return AllR::dispatch(pl.desc.R, [&](auto rc) {
-    return launch_r<decltype(rc)::value>(pl, zs, y, u, d, x_out, f_out, s);
+    return launch_r<decltype(rc)::value>(pl, zs, y, u, d, d_from_f ? 1 : 0, x_out, f_out, s);
   });
 }
 
