@@ -208,6 +208,34 @@ def bm3d_workload(steps):
             "ms_match_stage2": (st[2] - st[1]) * 1e3, "ms_filter_wiener_and_aggregate": (t_full - st[2]) * 1e3}
 
 
+def paper_schedule(steps):
+    """The bench workload under Algorithm 1's own schedule (Gauss-Seidel u-sweep over slices)."""
+    import torch
+
+    import synth
+    from paper_2511_03093_amd import cspnp
+    prob = synth.make(2)
+    pd = prob.params
+    NR, H, W = prob.gt.shape
+    plan = cspnp.Plan(prob.masks, denoiser="tv")
+    p = cspnp.params_from(pd, flags=cspnp.FLAG_PAPER_SCHEDULE)
+    y = torch.from_numpy(prob.y).cuda()
+    u = torch.zeros((NR, H, W), device="cuda")
+    d = torch.zeros((NR, H, W), device="cuda")
+    x = torch.empty((NR, H, W), device="cuda")
+    ws = plan.workspace(p)
+
+    def run():
+        u.zero_()
+        d.zero_()
+        plan.solve(p, y, u, d, x, ws)
+
+    t = timed(run, steps, 1)
+    plan.close()
+    return {"workload": "512x512x16 TV + temporal 0.1, 100 iterations, Gauss-Seidel u-sweep over slices",
+            "ms_per_solve": t * 1e3, "voxel_iters_per_s": NR * H * W * pd["iters"] / t}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -323,6 +351,7 @@ def main():
         out["batched"] = batched_vs_plain(a.extra_steps)
         out["differentiable"] = fwd_bwd(a.extra_steps)
         out["bm3d"] = bm3d_workload(2)
+        out["paper_schedule"] = paper_schedule(a.extra_steps)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, pd, a.cpu_iters)
     print(json.dumps(out), flush=True)

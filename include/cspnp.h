@@ -61,7 +61,13 @@ enum { CSPNP_DENOISER_TIKHONOV = 0, CSPNP_DENOISER_TV = 1, CSPNP_DENOISER_BM3D =
 /* cspnp_params.flags */
 enum {
   CSPNP_FLAG_NO_GRAPH = 1,     /* launch kernels one by one instead of replaying a captured graph */
-  CSPNP_FLAG_CHECK_FINITE = 2  /* after a solve, synchronise and fail with ENONFINITE on NaN/Inf in x */
+  CSPNP_FLAG_CHECK_FINITE = 2, /* after a solve, synchronise and fail with ENONFINITE on NaN/Inf in x */
+  /* cspnp_solve runs Algorithm 1's own schedule: the v-step without the temporal
+   * term (eq. (v-update)), then one Gauss-Seidel sweep over the slices of
+   * eq. (u-update) (datum (rho (v_n + d_n) + gamma (u_{n-1} + u_{n+1})) / (rho + 2 gamma),
+   * strength lambda / (rho + 2 gamma), newest neighbour values, periodic wrap or
+   * free ends), then d = d + v - u.  x returns v.  TV and Tikhonov denoisers. */
+  CSPNP_FLAG_PAPER_SCHEDULE = 4
 };
 
 /* workspace modes for cspnp_workspace_size */

@@ -20,6 +20,7 @@ ZBC = {"periodic": 0, "neumann": 1}
 DENOISER = {"tikhonov": 0, "tv": 1, "bm3d": 2}
 FLAG_NO_GRAPH = 1
 FLAG_CHECK_FINITE = 2
+FLAG_PAPER_SCHEDULE = 4
 WS_SOLVE, WS_DENOISE = 0, 1
 
 

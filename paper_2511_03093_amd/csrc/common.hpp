@@ -106,8 +106,14 @@ hipError_t launch_tikhonov(const cspnp_plan& pl, double lambda, double rho, cons
 size_t tv_workspace_bytes(const cspnp_plan& pl, int tv_inner);
 hipError_t launch_tv(const cspnp_plan& pl, double lambda, double rho, int tv_inner, double tau,
                      const float* f, float* u, float* d_out, void* ws, hipStream_t s);
+// nslices > 0: denoise only the first nslices slices starting at f/u/d_out (default: all).
 hipError_t launch_tv_shape(const cspnp_plan& pl, int shape, double lambda, double rho, int tv_inner,
-                           double tau, const float* f, float* u, float* d_out, void* ws, hipStream_t s);
+                           double tau, const float* f, float* u, float* d_out, void* ws, hipStream_t s,
+                           int nslices = 0);
+// Algorithm 1's own schedule (gamma on the u-block, Gauss-Seidel over slices).
+size_t paper_workspace_bytes(const cspnp_plan& pl, int tv_inner);
+hipError_t enqueue_paper_iterations(const cspnp_plan& pl, const cspnp_params& p, const float* y, float* u,
+                                    float* d, float* x, void* ws, hipStream_t s);
 size_t bm3d_workspace_bytes(const cspnp_plan& pl);
 void make_dct_matrix(double* c);  // 64 entries, row k = frequency
 hipError_t launch_bm3d(const cspnp_plan& pl, double sigma, const float* f, float* u, float* d_out, void* ws,

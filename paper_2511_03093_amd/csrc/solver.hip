@@ -24,6 +24,7 @@ size_t denoise_ws_bytes(const cspnp_plan& pl, const cspnp_params& p) {
 }
 
 size_t solve_ws_bytes(const cspnp_plan& pl, const cspnp_params& p) {
+  if (p.flags & CSPNP_FLAG_PAPER_SCHEDULE) return paper_workspace_bytes(pl, p.tv_inner);
   if (pl.desc.denoiser == CSPNP_DENOISER_TIKHONOV) return 0;
   // f = x + d between the x-step and the u-step, then the denoiser's own space
   return align_up(volume_elems(pl) * sizeof(float)) + denoise_ws_bytes(pl, p);
@@ -48,6 +49,7 @@ hipError_t enqueue_denoise(const cspnp_plan& pl, const cspnp_params& p, const fl
 
 hipError_t enqueue_iterations(const cspnp_plan& pl, const cspnp_params& p, const float* y, float* u,
                               float* d, float* x, void* ws, hipStream_t s) {
+  if (p.flags & CSPNP_FLAG_PAPER_SCHEDULE) return enqueue_paper_iterations(pl, p, y, u, d, x, ws, s);
   const ZSolve zs = make_zsolve(pl.desc.R, pl.desc.zbc, p.rho, p.gamma);
   if (pl.desc.denoiser == CSPNP_DENOISER_TIKHONOV) {
     for (int k = 0; k < p.iters; ++k) {
@@ -161,6 +163,8 @@ CSPNP_API int cspnp_solve(const cspnp_plan* cplan, const cspnp_params* params, c
   if (int s = check_ptr(d, "d")) return s;
   if (int s = check_ptr(x, "x")) return s;
   if (u == d || x == u || x == d) return fail(CSPNP_EINVAL, "u, d and x must be distinct buffers");
+  if ((params->flags & CSPNP_FLAG_PAPER_SCHEDULE) && cplan->desc.denoiser == CSPNP_DENOISER_BM3D)
+    return fail(CSPNP_EUNSUPPORTED, "the paper schedule is implemented for the TV and Tikhonov denoisers");
   if (int s = check_ws(*cplan, solve_ws_bytes(*cplan, *params), ws)) return s;
   cspnp_plan* plan = const_cast<cspnp_plan*>(cplan);  // the graph cache is mutable state
   hipStream_t st = as_stream(stream);
@@ -170,7 +174,8 @@ CSPNP_API int cspnp_solve(const cspnp_plan* cplan, const cspnp_params* params, c
   } else {
     std::vector<uint8_t> key;
     cspnp_params pk = *params;
-    pk.flags = 0;
+    pk.flags &= CSPNP_FLAG_PAPER_SCHEDULE;  // the schedule changes the graph; other flags do not
+    append(key, pk.flags);
     append(key, pk.lambda); append(key, pk.rho); append(key, pk.gamma); append(key, pk.iters);
     append(key, pk.tv_inner); append(key, pk.tv_tau); append(key, pk.bm3d_sigma);
     append(key, y); append(key, u); append(key, d); append(key, x); append(key, ws);

@@ -101,9 +101,10 @@ hipError_t launch_tv(const cspnp_plan& pl, double lambda, double rho, int tv_inn
 }
 
 hipError_t launch_tv_shape(const cspnp_plan& pl, int shape, double lambda, double rho, int tv_inner,
-                           double tau, const float* f, float* u, float* d_out, void* ws, hipStream_t st) {
+                           double tau, const float* f, float* u, float* d_out, void* ws, hipStream_t st,
+                           int nslices) {
   const auto& de = pl.desc;
-  const int NR = de.N * de.R;
+  const int NR = nslices > 0 ? nslices : de.N * de.R;
   TvLaunch a{};
   a.f = f;
   a.u = u;
