@@ -71,7 +71,7 @@ enum {
 };
 
 /* workspace modes for cspnp_workspace_size */
-enum { CSPNP_WS_SOLVE = 0, CSPNP_WS_DENOISE = 1 };
+enum { CSPNP_WS_SOLVE = 0, CSPNP_WS_DENOISE = 1, CSPNP_WS_SOLVE_TOL = 2 };
 
 /* Problem shape: H x W pixels, R masks/slices per shot, N shots (Sec. III-A). */
 typedef struct cspnp_desc {
@@ -166,6 +166,33 @@ int cspnp_denoise(const cspnp_plan* plan, const cspnp_params* params, const floa
  * that later identical calls replay. */
 int cspnp_solve(const cspnp_plan* plan, const cspnp_params* params, const float* y, float* u,
                 float* d, float* x, void* ws, void* stream);
+
+/* Algorithm 1 with a stopping rule (Sec. IV-B caps the iterations and uses a
+ * relative tolerance it does not define; read here as
+ * ||x^{k+1} - x^k|| / ||x^k|| < tol): at most params->iters iterations, the
+ * relative change of consecutive x-steps tested every check_every iterations
+ * (one host synchronisation per test).  *iters_done receives the iterations
+ * run, *last_rel the last tested change (-1 if none).  Synchronous.
+ * ws: cspnp_workspace_size(CSPNP_WS_SOLVE_TOL) bytes. */
+int cspnp_solve_tol(const cspnp_plan* plan, const cspnp_params* params, double tol, int check_every,
+                    const float* y, float* u, float* d, float* x, void* ws, void* stream, int32_t* iters_done,
+                    double* last_rel);
+
+/* ---- quality metrics (Sec. IV) --------------------------------------------
+ * PSNR = 10 log10(n peak^2 / ||est - ref||^2) over n elements (3D: all voxels
+ * as one array).  SSIM: window-weighted local statistics with an 11-tap
+ * Gaussian (standard deviation 1.5, normalised) along W and H (dims = 2, per
+ * slice) or W, H and D (dims = 3), c1 = (0.01 L)^2, c2 = (0.03 L)^2, averaged
+ * over all positions where the window lies inside the data (needs H, W >= 11,
+ * and D >= 11 for dims = 3).  cspnp_rel_change = ||a - b|| / ||b||.  Inputs are
+ * device float arrays ([D][H][W] for SSIM); `out` is one device double,
+ * written asynchronously; ws: cspnp_metrics_workspace_size(D, H, W, dims)
+ * bytes (dims = 0 for PSNR and the relative change), 256-byte aligned. */
+int cspnp_metrics_workspace_size(int32_t D, int32_t H, int32_t W, int32_t dims, size_t* bytes);
+int cspnp_psnr(const float* est, const float* ref, size_t n, double peak, double* out, void* ws, void* stream);
+int cspnp_ssim(const float* est, const float* ref, int32_t D, int32_t H, int32_t W, int32_t dims, double L,
+               double* out, void* ws, void* stream);
+int cspnp_rel_change(const float* a, const float* b, size_t n, double* out, void* ws, void* stream);
 
 /* ---- BM3D stage inspection ------------------------------------------------
  * The BM3D u-step (plan denoiser CSPNP_DENOISER_BM3D, params->bm3d_sigma the

@@ -21,7 +21,7 @@ DENOISER = {"tikhonov": 0, "tv": 1, "bm3d": 2}
 FLAG_NO_GRAPH = 1
 FLAG_CHECK_FINITE = 2
 FLAG_PAPER_SCHEDULE = 4
-WS_SOLVE, WS_DENOISE = 0, 1
+WS_SOLVE, WS_DENOISE, WS_SOLVE_TOL = 0, 1, 2
 
 
 class Desc(ctypes.Structure):
@@ -70,6 +70,13 @@ _SIGNATURES = {
                                  ctypes.c_int),
     "cspnp_solve_ckpt": ([_P, ctypes.POINTER(Params), _P, _P, _P, _P, ctypes.c_int, _P, _P, _P], ctypes.c_int),
     "cspnp_solve_bwd": ([_P, ctypes.POINTER(Params), _P, ctypes.c_int, _P, _P, _P, _P, _P, _P], ctypes.c_int),
+    "cspnp_solve_tol": ([_P, ctypes.POINTER(Params), ctypes.c_double, ctypes.c_int, _P, _P, _P, _P, _P, _P,
+                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "cspnp_metrics_workspace_size": ([ctypes.c_int32] * 4 + [ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "cspnp_psnr": ([_P, _P, ctypes.c_size_t, ctypes.c_double, _P, _P, _P], ctypes.c_int),
+    "cspnp_ssim": ([_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, _P, _P,
+                    _P], ctypes.c_int),
+    "cspnp_rel_change": ([_P, _P, ctypes.c_size_t, _P, _P, _P], ctypes.c_int),
     "cspnp_bm3d_stage": ([_P, ctypes.POINTER(Params), _P, ctypes.c_int, _P, _P], ctypes.c_int),
     "cspnp_bm3d_layout": ([_P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
                            ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_int32),
@@ -253,6 +260,61 @@ def cspnp_solve_bwd(plan, params, y, ckpt_every, ckpt, x_bar, y_bar, param_bar, 
           _P(param_bar), _P(ws), _P(stream))
 
 
+def cspnp_solve_tol(plan, params, tol, check_every, y, u, d, x, ws, stream):
+    it = ctypes.c_int32()
+    rel = ctypes.c_double()
+    _call("cspnp_solve_tol", plan, ctypes.byref(params), float(tol), int(check_every), _P(y), _P(u), _P(d), _P(x),
+          _P(ws), _P(stream), ctypes.byref(it), ctypes.byref(rel))
+    return it.value, rel.value
+
+
+def cspnp_metrics_workspace_size(D, H, W, dims):
+    n = ctypes.c_size_t()
+    _call("cspnp_metrics_workspace_size", int(D), int(H), int(W), int(dims), ctypes.byref(n))
+    return n.value
+
+
+def cspnp_psnr(est, ref, n, peak, out, ws, stream):
+    _call("cspnp_psnr", _P(est), _P(ref), int(n), float(peak), _P(out), _P(ws), _P(stream))
+
+
+def cspnp_ssim(est, ref, D, H, W, dims, L, out, ws, stream):
+    _call("cspnp_ssim", _P(est), _P(ref), int(D), int(H), int(W), int(dims), float(L), _P(out), _P(ws), _P(stream))
+
+
+def cspnp_rel_change(a, b, n, out, ws, stream):
+    _call("cspnp_rel_change", _P(a), _P(b), int(n), _P(out), _P(ws), _P(stream))
+
+
+def _metric(fn_name, dims, est, ref, *extra):
+    """Run one metric on device tensors; returns the Python float."""
+    torch = _torch()
+    D, H, W = est.shape if est.dim() == 3 else (1, *est.shape[-2:])
+    nb = cspnp_metrics_workspace_size(D, H, W, dims)
+    ws = torch.empty(nb + 256, dtype=torch.uint8, device="cuda")
+    out = torch.empty(1, dtype=torch.float64, device="cuda")
+    wsp = (ws.data_ptr() + 255) & ~255
+    if fn_name == "psnr":
+        cspnp_psnr(_ptr(est, "est"), _ptr(ref, "ref"), est.numel(), extra[0], out.data_ptr(), wsp, _stream())
+    elif fn_name == "ssim":
+        cspnp_ssim(_ptr(est, "est"), _ptr(ref, "ref"), D, H, W, dims, extra[0], out.data_ptr(), wsp, _stream())
+    else:
+        cspnp_rel_change(_ptr(est, "a"), _ptr(ref, "b"), est.numel(), out.data_ptr(), wsp, _stream())
+    return float(out.item())
+
+
+def psnr(est, ref, peak=1.0):
+    return _metric("psnr", 0, est, ref, peak)
+
+
+def ssim(est, ref, dims=2, L=1.0):
+    return _metric("ssim", dims, est, ref, L)
+
+
+def rel_change(a, b):
+    return _metric("rel", 0, a, b)
+
+
 def cspnp_bm3d_stage(plan, params, f, stage, ws, stream):
     _call("cspnp_bm3d_stage", plan, ctypes.byref(params), _P(f), int(stage), _P(ws), _P(stream))
 
@@ -424,6 +486,19 @@ class Plan:
     def autotune(self, params, cache_path=None, force=False):
         cspnp_autotune(self._handle, params, cache_path, force, _stream())
         return self.tuning()
+
+    def solve_tol(self, params, y, tol, check_every=1, u=None, d=None, x=None):
+        """Iterate until the relative change of x drops below tol (at most params.iters); returns
+        (x, u, d, iterations, last relative change)."""
+        torch = _torch()
+        u = torch.zeros(self.vol_shape, dtype=torch.float32, device="cuda") if u is None else u
+        d = torch.zeros(self.vol_shape, dtype=torch.float32, device="cuda") if d is None else d
+        x = self._empty(self.vol_shape) if x is None else x
+        ws = self.workspace(params, WS_SOLVE_TOL)
+        it, rel = cspnp_solve_tol(self._handle, params, tol, check_every, _ptr(y, "y", self.frame_shape),
+                                  _ptr(u, "u", self.vol_shape), _ptr(d, "d", self.vol_shape),
+                                  _ptr(x, "x", self.vol_shape), self._ws_ptr(ws), _stream())
+        return x, u, d, it, rel
 
     def solve(self, params, y, u=None, d=None, x=None, ws=None):
         """Run params.iters iterations in place on (u, d); returns (x, u, d)."""

@@ -89,11 +89,7 @@ int write_cache(const char* path, const std::map<std::string, Entry>& m) {
   return CSPNP_OK;
 }
 
-void invalidate_graph(cspnp_plan& pl) {
-  if (pl.graph.exec) { (void)hipGraphExecDestroy(pl.graph.exec); pl.graph.exec = nullptr; }
-  if (pl.graph.graph) { (void)hipGraphDestroy(pl.graph.graph); pl.graph.graph = nullptr; }
-  pl.graph.key.clear();
-}
+void invalidate_graph(cspnp_plan& pl) { pl.graph.clear(); }
 
 struct DevBuf {
   void* p = nullptr;

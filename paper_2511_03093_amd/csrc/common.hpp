@@ -61,10 +61,51 @@ struct TvShapeInfo {
   int cols, rows; // tile size in pixels
 };
 
-struct GraphCache {
+// Captured iteration graphs of a plan, keyed by (parameters, pointers); a few
+// are kept (least recently used evicted) so alternating call patterns replay.
+struct GraphEntry {
   std::vector<uint8_t> key;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  uint64_t last_use = 0;
+};
+
+struct GraphCache {
+  static constexpr size_t kMax = 4;
+  std::vector<GraphEntry> entries;
+  uint64_t clock = 0;
+  GraphEntry* find(const std::vector<uint8_t>& key) {
+    for (auto& e : entries)
+      if (e.exec && e.key == key) {
+        e.last_use = ++clock;
+        return &e;
+      }
+    return nullptr;
+  }
+  // an empty entry (evicting the least recently used one when full)
+  GraphEntry& slot() {
+    if (entries.size() < kMax) {
+      entries.emplace_back();
+      return entries.back();
+    }
+    GraphEntry* lru = &entries[0];
+    for (auto& e : entries)
+      if (e.last_use < lru->last_use) lru = &e;
+    release(*lru);
+    return *lru;
+  }
+  static void release(GraphEntry& e) {
+    if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    if (e.graph) (void)hipGraphDestroy(e.graph);
+    e.exec = nullptr;
+    e.graph = nullptr;
+    e.key.clear();
+  }
+  void clear() {
+    for (auto& e : entries) release(e);
+    entries.clear();
+  }
+  ~GraphCache() { clear(); }
 };
 
 }  // namespace cspnp
@@ -110,6 +151,8 @@ hipError_t launch_tv(const cspnp_plan& pl, double lambda, double rho, int tv_inn
 hipError_t launch_tv_shape(const cspnp_plan& pl, int shape, double lambda, double rho, int tv_inner,
                            double tau, const float* f, float* u, float* d_out, void* ws, hipStream_t s,
                            int nslices = 0);
+hipError_t launch_rel_change(const float* a, const float* b, size_t n, double* out, void* ws, hipStream_t s);
+size_t rel_change_ws_bytes();
 // Algorithm 1's own schedule (gamma on the u-block, Gauss-Seidel over slices).
 size_t paper_workspace_bytes(const cspnp_plan& pl, int tv_inner);
 hipError_t enqueue_paper_iterations(const cspnp_plan& pl, const cspnp_params& p, const float* y, float* u,

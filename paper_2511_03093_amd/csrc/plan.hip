@@ -127,8 +127,7 @@ static int ensure_device(int* dev_out) {
 using namespace cspnp;
 
 cspnp_plan::~cspnp_plan() {
-  if (graph.exec) (void)hipGraphExecDestroy(graph.exec);
-  if (graph.graph) (void)hipGraphDestroy(graph.graph);
+  graph.clear();
   if (capture_stream) (void)hipStreamDestroy(capture_stream);
   if (bits) (void)hipFree(bits);
   if (dct) (void)hipFree(dct);

@@ -2,6 +2,7 @@
 // (Algorithm 1 with the temporal term in the x-step).  The iteration loop of
 // cspnp_solve is captured once into a HIP graph per (parameters, pointers)
 // and replayed on the caller's stream.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -98,6 +99,9 @@ CSPNP_API int cspnp_workspace_size(const cspnp_plan* plan, const cspnp_params* p
   if (int s = validate_params(plan, params)) return s;
   if (bytes == nullptr) return fail(CSPNP_EINVAL, "bytes is NULL");
   if (mode == CSPNP_WS_SOLVE) *bytes = solve_ws_bytes(*plan, *params);
+  else if (mode == CSPNP_WS_SOLVE_TOL)
+    *bytes = align_up(solve_ws_bytes(*plan, *params)) + align_up(volume_elems(*plan) * sizeof(float)) +
+             rel_change_ws_bytes() + 256;
   else if (mode == CSPNP_WS_DENOISE) *bytes = denoise_ws_bytes(*plan, *params);
   else return fail(CSPNP_EINVAL, "unknown workspace mode");
   return CSPNP_OK;
@@ -179,10 +183,8 @@ CSPNP_API int cspnp_solve(const cspnp_plan* cplan, const cspnp_params* params, c
     append(key, pk.lambda); append(key, pk.rho); append(key, pk.gamma); append(key, pk.iters);
     append(key, pk.tv_inner); append(key, pk.tv_tau); append(key, pk.bm3d_sigma);
     append(key, y); append(key, u); append(key, d); append(key, x); append(key, ws);
-    GraphCache& gc = plan->graph;
-    if (!(gc.exec && gc.key == key)) {
-      if (gc.exec) { (void)hipGraphExecDestroy(gc.exec); gc.exec = nullptr; }
-      if (gc.graph) { (void)hipGraphDestroy(gc.graph); gc.graph = nullptr; }
+    GraphEntry* ge = plan->graph.find(key);
+    if (!ge) {
       CSPNP_HIP(hipStreamBeginCapture(plan->capture_stream, hipStreamCaptureModeThreadLocal));
       hipError_t e = enqueue_iterations(*plan, *params, y, u, d, x, ws, plan->capture_stream);
       hipGraph_t g = nullptr;
@@ -192,12 +194,59 @@ CSPNP_API int cspnp_solve(const cspnp_plan* cplan, const cspnp_params* params, c
       hipGraphExec_t ex = nullptr;
       hipError_t e3 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
       if (e3 != hipSuccess) { (void)hipGraphDestroy(g); return hip_fail(e3, "hipGraphInstantiate"); }
-      gc.graph = g;
-      gc.exec = ex;
-      gc.key = key;
+      ge = &plan->graph.slot();
+      ge->graph = g;
+      ge->exec = ex;
+      ge->key = key;
+      ge->last_use = ++plan->graph.clock;
     }
-    CSPNP_HIP(hipGraphLaunch(gc.exec, st));
+    CSPNP_HIP(hipGraphLaunch(ge->exec, st));
   }
   if (params->flags & CSPNP_FLAG_CHECK_FINITE) return check_finite_x(*plan, x, st);
+  return CSPNP_OK;
+}
+
+CSPNP_API int cspnp_solve_tol(const cspnp_plan* plan, const cspnp_params* params, double tol, int check_every,
+                              const float* y, float* u, float* d, float* x, void* ws, void* stream,
+                              int32_t* iters_done, double* last_rel) {
+  clear_error();
+  if (int s = validate_plan(plan)) return s;
+  if (int s = validate_params(plan, params)) return s;
+  if (!(tol >= 0) || check_every < 1) return fail(CSPNP_EINVAL, "tol must be >= 0 and check_every >= 1");
+  if (!iters_done || !last_rel) return fail(CSPNP_EINVAL, "iters_done and last_rel must not be NULL");
+  if (!ws || reinterpret_cast<uintptr_t>(ws) % 256) return fail(CSPNP_EINVAL, "ws must be 256-byte aligned");
+  hipStream_t st = as_stream(stream);
+  const size_t vol = volume_elems(*plan);
+  const size_t solve_ws = align_up(solve_ws_bytes(*plan, *params));
+  char* w = static_cast<char*>(ws);
+  float* x_prev = reinterpret_cast<float*>(w + solve_ws);
+  char* red = w + solve_ws + align_up(vol * sizeof(float));
+  double* rel_dev = reinterpret_cast<double*>(red + rel_change_ws_bytes());
+  *iters_done = 0;
+  *last_rel = -1.0;
+  const int K = params->iters;
+  int k = 0;
+  cspnp_params p = *params;
+  while (k < K) {
+    const int n = std::min(check_every, K - k);
+    if (n > 1) {
+      p.iters = n - 1;
+      if (int s = cspnp_solve(plan, &p, y, u, d, x, ws, stream)) return s;
+    }
+    const bool have_prev = k + n - 1 >= 1;  // x holds the previous x-step
+    if (have_prev) CSPNP_HIP(hipMemcpyAsync(x_prev, x, vol * sizeof(float), hipMemcpyDeviceToDevice, st));
+    p.iters = 1;
+    if (int s = cspnp_solve(plan, &p, y, u, d, x, ws, stream)) return s;
+    k += n;
+    *iters_done = k;
+    if (have_prev) {
+      CSPNP_HIP(launch_rel_change(x, x_prev, vol, rel_dev, red, st));
+      double rel = 0.0;
+      CSPNP_HIP(hipMemcpyAsync(&rel, rel_dev, sizeof rel, hipMemcpyDeviceToHost, st));
+      CSPNP_HIP(hipStreamSynchronize(st));
+      *last_rel = rel;
+      if (rel < tol) break;
+    }
+  }
   return CSPNP_OK;
 }
