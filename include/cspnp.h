@@ -46,7 +46,7 @@ typedef enum cspnp_status {
   CSPNP_ENOMEM = 2,       /* host or device allocation failed */
   CSPNP_EHIP = 3,         /* a HIP runtime call failed (includes earlier asynchronous faults) */
   CSPNP_ENODEV = 4,       /* no usable gfx950 device */
-  CSPNP_EUNSUPPORTED = 5, /* valid request this build does not implement */
+  CSPNP_EUNSUPPORTED = 5, /* valid request this build does not implement (e.g. the backward with N > 1) */
   CSPNP_ENONFINITE = 6    /* non-finite value detected (only with CSPNP_FLAG_CHECK_FINITE) */
 } cspnp_status;
 
@@ -77,7 +77,7 @@ enum { CSPNP_WS_SOLVE = 0, CSPNP_WS_DENOISE = 1, CSPNP_WS_SOLVE_TOL = 2 };
 typedef struct cspnp_desc {
   int32_t H, W;
   int32_t R;        /* compression ratio, 1..32 */
-  int32_t N;        /* shots per volume; this build supports N = 1 */
+  int32_t N;        /* shots per volume, N*R <= 1024 (N > 1: no backward, no batching) */
   int32_t zbc;      /* CSPNP_ZBC_* */
   int32_t denoiser; /* CSPNP_DENOISER_* */
 } cspnp_desc;

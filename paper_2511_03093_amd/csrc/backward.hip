@@ -462,6 +462,7 @@ int validate_diff(const cspnp_plan* plan, const cspnp_params* p, int c) {
   if (int s = validate_plan(plan)) return s;
   if (int s = validate_params(plan, p)) return s;
   if (c < 1) return fail(CSPNP_EINVAL, "ckpt_every must be >= 1");
+  if (plan->desc.N != 1) return fail(CSPNP_EUNSUPPORTED, "the backward is implemented for N = 1 shot");
   if (plan->desc.denoiser == CSPNP_DENOISER_BM3D)
     return fail(CSPNP_EUNSUPPORTED, "the backward is implemented for the TV and Tikhonov denoisers");
   if (plan->desc.denoiser == CSPNP_DENOISER_TV && p->tv_inner > 16)

@@ -327,6 +327,7 @@ CSPNP_API int cspnp_batch_create(int32_t n, const cspnp_desc* descs, const uint8
   std::unique_ptr<cspnp_batch> b(new cspnp_batch());
   for (int i = 0; i < n; ++i) {
     if (descs[i].denoiser != CSPNP_DENOISER_TV) return fail(CSPNP_EUNSUPPORTED, "batched solves use the TV denoiser");
+    if (descs[i].N != 1) return fail(CSPNP_EUNSUPPORTED, "batched solves take N = 1 shot per problem");
     cspnp_plan* p = nullptr;
     if (int s = cspnp_plan_create(&descs[i], masks[i], 0, stream, &p)) return s;
     b->plans.push_back(p);

@@ -120,6 +120,7 @@ struct cspnp_plan {
   int tv_shape = 0;  // index into the TV tile-shape table
   int xu_block = 0;  // index into the x-update block-shape table
   double* dct = nullptr;  // device 8x8 DCT-II matrix (BM3D plans)
+  double* ms_scratch = nullptr;  // FP64 scratch of the multi-shot x-step (N > 1)
   ~cspnp_plan();
 };
 
@@ -151,6 +152,9 @@ hipError_t launch_tv(const cspnp_plan& pl, double lambda, double rho, int tv_inn
 hipError_t launch_tv_shape(const cspnp_plan& pl, int shape, double lambda, double rho, int tv_inner,
                            double tau, const float* f, float* u, float* d_out, void* ws, hipStream_t s,
                            int nslices = 0);
+size_t multishot_scratch_bytes(const cspnp_desc& de);
+hipError_t launch_xupdate_multishot(const cspnp_plan& pl, double rho, double gamma, const float* y, const float* u,
+                                    const float* d, bool d_from_f, float* x_out, float* f_out, hipStream_t s);
 hipError_t launch_rel_change(const float* a, const float* b, size_t n, double* out, void* ws, hipStream_t s);
 size_t rel_change_ws_bytes();
 // Algorithm 1's own schedule (gamma on the u-block, Gauss-Seidel over slices).

@@ -37,7 +37,7 @@ static int validate_desc(const cspnp_desc* d) {
   if (d->H < 1 || d->W < 1) return fail(CSPNP_EINVAL, "H and W must be >= 1");
   if (d->R < 1 || d->R > kMaxR) return fail(CSPNP_EINVAL, "R must be in [1, 32]");
   if (d->N < 1) return fail(CSPNP_EINVAL, "N must be >= 1");
-  if (d->N != 1) return fail(CSPNP_EUNSUPPORTED, "N > 1 shots per volume is not implemented");
+  if ((int64_t)d->N * d->R > 1024) return fail(CSPNP_EINVAL, "N*R must be <= 1024");
   if (d->zbc != CSPNP_ZBC_PERIODIC && d->zbc != CSPNP_ZBC_NEUMANN)
     return fail(CSPNP_EINVAL, "zbc must be CSPNP_ZBC_PERIODIC or CSPNP_ZBC_NEUMANN");
   if (d->denoiser != CSPNP_DENOISER_TIKHONOV && d->denoiser != CSPNP_DENOISER_TV &&
@@ -131,6 +131,7 @@ cspnp_plan::~cspnp_plan() {
   if (capture_stream) (void)hipStreamDestroy(capture_stream);
   if (bits) (void)hipFree(bits);
   if (dct) (void)hipFree(dct);
+  if (ms_scratch) (void)hipFree(ms_scratch);
 }
 
 CSPNP_API int cspnp_version(void) { return CSPNP_VERSION; }
@@ -196,6 +197,7 @@ CSPNP_API int cspnp_plan_create(const cspnp_desc* desc, const uint8_t* masks, in
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   CSPNP_HIP(hipMemcpyAsync(plan->bits, packed.data(), packed.size() * sizeof(uint32_t),
                            hipMemcpyHostToDevice, st));
+  if (desc->N > 1) CSPNP_HIP(hipMalloc(&plan->ms_scratch, multishot_scratch_bytes(*desc)));
   if (desc->denoiser == CSPNP_DENOISER_BM3D) {
     double c[64];
     make_dct_matrix(c);

@@ -26,7 +26,7 @@ size_t denoise_ws_bytes(const cspnp_plan& pl, const cspnp_params& p) {
 
 size_t solve_ws_bytes(const cspnp_plan& pl, const cspnp_params& p) {
   if (p.flags & CSPNP_FLAG_PAPER_SCHEDULE) return paper_workspace_bytes(pl, p.tv_inner);
-  if (pl.desc.denoiser == CSPNP_DENOISER_TIKHONOV) return 0;
+  if (pl.desc.denoiser == CSPNP_DENOISER_TIKHONOV && pl.desc.N == 1) return 0;
   // f = x + d between the x-step and the u-step, then the denoiser's own space
   return align_up(volume_elems(pl) * sizeof(float)) + denoise_ws_bytes(pl, p);
 }
@@ -52,7 +52,7 @@ hipError_t enqueue_iterations(const cspnp_plan& pl, const cspnp_params& p, const
                               float* d, float* x, void* ws, hipStream_t s) {
   if (p.flags & CSPNP_FLAG_PAPER_SCHEDULE) return enqueue_paper_iterations(pl, p, y, u, d, x, ws, s);
   const ZSolve zs = make_zsolve(pl.desc.R, pl.desc.zbc, p.rho, p.gamma);
-  if (pl.desc.denoiser == CSPNP_DENOISER_TIKHONOV) {
+  if (pl.desc.denoiser == CSPNP_DENOISER_TIKHONOV && pl.desc.N == 1) {
     for (int k = 0; k < p.iters; ++k) {
       hipError_t e = launch_xupdate_tikhonov(pl, zs, p.lambda, y, u, d, k == p.iters - 1 ? x : nullptr, s);
       if (e != hipSuccess) return e;

@@ -152,6 +152,7 @@ void xu_block_info(int i, int* bx, int* by) {
 
 hipError_t launch_xupdate(const cspnp_plan& pl, const ZSolve& zs, const float* y, const float* u,
                           const float* d, float* x_out, float* f_out, hipStream_t s, bool d_from_f) {
+  if (pl.desc.N > 1) return launch_xupdate_multishot(pl, zs.rho, zs.gamma, y, u, d, d_from_f, x_out, f_out, s);
   return AllR::dispatch(pl.desc.R, [&](auto rc) {
     return launch_r<decltype(rc)::value>(pl, zs, y, u, d, d_from_f ? 1 : 0, x_out, f_out, s);
   });

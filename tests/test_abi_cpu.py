@@ -39,8 +39,8 @@ def test_plan_create_validation(lib):
     assert st == cspnp.EINVAL
     st, _ = _create(cspnp.Desc(0, 8, 4, 1, 0, 1), m)
     assert st == cspnp.EINVAL
-    st, _ = _create(cspnp.Desc(8, 8, 4, 2, 0, 1), m)
-    assert st == cspnp.EUNSUPPORTED
+    st, _ = _create(cspnp.Desc(8, 8, 4, 300, 0, 1), m)
+    assert st == cspnp.EINVAL and "N*R" in cspnp.cspnp_last_error()
     st, _ = _create(cspnp.Desc(8, 8, 4, 1, 7, 1), m)
     assert st == cspnp.EINVAL and "zbc" in cspnp.cspnp_last_error()
     st, _ = _create(cspnp.Desc(8, 8, 4, 1, 0, 9), m)
