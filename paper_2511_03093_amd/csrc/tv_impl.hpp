@@ -31,6 +31,24 @@ __device__ __forceinline__ float from_right(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, true));
 }
 
+// Buffer resources over one H x W slice.  Every offset the tile uses is clamped
+// into the slice, so the hardware range check is never what keeps an access in
+// bounds; the resource form lets a load take the wave-uniform row offset in an
+// SGPR and the lane's column offset in a 32-bit VGPR (no 64-bit address math).
+// Plans keep H*W <= 2^30, so every offset fits the 32-bit byte range.
+using Rsrc = __amdgpu_buffer_rsrc_t;
+__device__ __forceinline__ Rsrc slice_rsrc(const float* p, int H, int W) {
+  const uint64_t bytes = (uint64_t)H * (uint64_t)W * 4u;
+  const uint32_t n = bytes > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)bytes;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(p), (short)0, (int)n, 0x00020000);
+}
+__device__ __forceinline__ float ld(Rsrc r, uint32_t voff, uint32_t soff) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ void st(float v, Rsrc r, uint32_t voff, uint32_t soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)voff, (int)soff, 0);
+}
+
 // LDS exchange between vertically adjacent waves, double-buffered by inner-iteration parity:
 // [parity][wave][0] = the wave's bottom-row p_y, [parity][wave][1] = its top-row partial
 // divergence (px - px_left) + py.  Every w is evaluated as (((px - px_left) + py) - py_up) - f/theta,
@@ -38,7 +56,10 @@ __device__ __forceinline__ float from_right(float v) {
 template <int CX, int NW>
 using TvExchange = float[2][NW][2][64 * CX];
 
-template <int CX, int S, int NW, bool BORDER>
+// BX: the tile reaches a column outside [0, W-1), so the x-gradient needs its
+// boundary mask.  Rows without a y-gradient (the last image row, and rows outside
+// the image) are wave-uniform and take a branch of their own.
+template <int CX, int S, int NW, bool BX>
 __device__ __forceinline__ void tv_tile_impl(const TvLaunch& a, const int k, const int L, const int ox, const int oy,
                                              const size_t base, TvExchange<CX, NW>& xch) {
   // No implicit contraction: a p value must round identically whether its
@@ -46,37 +67,73 @@ __device__ __forceinline__ void tv_tile_impl(const TvLaunch& a, const int k, con
   // intended fused multiply-adds are written as fmaf).
 #pragma clang fp contract(off)
   const int c0 = ox + L * CX;
-  const int r0 = oy + k * S;
-  const float* __restrict__ fn = a.f + base;
+  const int r0 = oy + k * S;  // wave-uniform
 
-  float px[S][CX], py[S][CX], fs[S][CX], fsb[CX];
+  // lane column byte offsets (clamped into the slice) and column masks
+  uint32_t coff[CX];
   float colx[CX];
 #pragma unroll
   for (int c = 0; c < CX; ++c) {
     const int gc = c0 + c;
+    coff[c] = 4u * (uint32_t)min(max(gc, 0), a.W - 1);
     colx[c] = (gc >= 0 && gc < a.W - 1) ? 1.f : 0.f;
   }
+  auto col_in = [&](int c) { return c0 + c >= 0 && c0 + c < a.W; };
+  auto row_off = [&](int s) -> uint32_t { return 4u * (uint32_t)min(max(r0 + s, 0), a.H - 1) * (uint32_t)a.W; };
+  // bit s set: row r0 + s lies in the image (s = 0..S) / has a y-gradient (r0 + s < H - 1)
+  uint32_t rows_in = 0, rows_gy = 0;
 #pragma unroll
   for (int s = 0; s <= S; ++s) {
     const int gr = r0 + s;
-    const bool rin = gr >= 0 && gr < a.H;
+    rows_in |= (gr >= 0 && gr < a.H) ? (1u << s) : 0u;
+    rows_gy |= (gr >= 0 && gr < a.H - 1) ? (1u << s) : 0u;
+  }
+  rows_in = __builtin_amdgcn_readfirstlane(rows_in);
+  rows_gy = __builtin_amdgcn_readfirstlane(rows_gy);
+
+  const Rsrc fr = slice_rsrc(a.f + base, a.H, a.W);
+  float px[S][CX], py[S][CX], fs[S][CX], fsb[CX];
+  {
+    // every load in flight at once, masked afterwards
+    float raw[S + 1][CX];
 #pragma unroll
-    for (int c = 0; c < CX; ++c) {
-      const int gc = c0 + c;
-      const bool in = rin && gc >= 0 && gc < a.W;
-      const size_t off = (size_t)gr * a.W + gc;
-      const float v = in ? __fmul_rn(fn[off], a.inv_theta) : 0.f;
-      if (s == S) {
-        fsb[c] = v;  // the first row of the wave below (its w is rebuilt here)
-        continue;
+    for (int s = 0; s <= S; ++s) {
+      const uint32_t ro = row_off(s);
+#pragma unroll
+      for (int c = 0; c < CX; ++c) raw[s][c] = ld(fr, coff[c], ro);
+    }
+    if (a.p_in) {
+      const Rsrc xr = slice_rsrc(a.p_in + base, a.H, a.W);
+      const Rsrc yr = slice_rsrc(a.p_in + a.vol + base, a.H, a.W);
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const uint32_t ro = row_off(s);
+#pragma unroll
+        for (int c = 0; c < CX; ++c) {
+          px[s][c] = ld(xr, coff[c], ro);
+          py[s][c] = ld(yr, coff[c], ro);
+        }
       }
-      fs[s][c] = v;
-      if (a.p_in) {
-        px[s][c] = in ? a.p_in[base + off] : 0.f;
-        py[s][c] = in ? a.p_in[a.vol + base + off] : 0.f;
-      } else {
-        px[s][c] = 0.f;
-        py[s][c] = 0.f;
+    } else {
+#pragma unroll
+      for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int c = 0; c < CX; ++c) px[s][c] = py[s][c] = 0.f;
+    }
+#pragma unroll
+    for (int s = 0; s <= S; ++s) {
+      const bool rin = (rows_in >> s) & 1u;
+#pragma unroll
+      for (int c = 0; c < CX; ++c) {
+        const bool in = rin && (!BX || col_in(c));
+        const float v = in ? __fmul_rn(raw[s][c], a.inv_theta) : 0.f;
+        if (s == S) {
+          fsb[c] = v;  // the first row of the wave below (its w is rebuilt here)
+          continue;
+        }
+        fs[s][c] = v;
+        px[s][c] = in ? px[s][c] : 0.f;
+        py[s][c] = in ? py[s][c] : 0.f;
       }
     }
   }
@@ -123,17 +180,27 @@ __device__ __forceinline__ void tv_tile_impl(const TvLaunch& a, const int k, con
         for (int c = 0; c < CX; ++c) wnext[c] = wbl[c];
       }
       const float right = from_right(wcur[0]);
-      const int gr = r0 + s;
-      const bool ry = gr >= 0 && gr < a.H - 1;  // wave-uniform
+      if ((rows_gy >> s) & 1u) {
 #pragma unroll
-      for (int c = 0; c < CX; ++c) {
-        const float wr = (c < CX - 1) ? wcur[c + 1] : right;
-        const float gx = BORDER ? (wr - wcur[c]) * colx[c] : (wr - wcur[c]);
-        const float gy = BORDER ? (ry ? (wnext[c] - wcur[c]) : 0.f) : (wnext[c] - wcur[c]);
-        const float q = fmaf(gx, gx, gy * gy);
-        const float rs = __builtin_amdgcn_rcpf(fmaf(tau, __builtin_amdgcn_sqrtf(q), 1.f));
-        px[s][c] = fmaf(tau, gx, px[s][c]) * rs;
-        py[s][c] = fmaf(tau, gy, py[s][c]) * rs;
+        for (int c = 0; c < CX; ++c) {
+          const float wr = (c < CX - 1) ? wcur[c + 1] : right;
+          const float gx = BX ? (wr - wcur[c]) * colx[c] : (wr - wcur[c]);
+          const float gy = wnext[c] - wcur[c];
+          const float q = fmaf(gx, gx, gy * gy);
+          const float rs = __builtin_amdgcn_rcpf(fmaf(tau, __builtin_amdgcn_sqrtf(q), 1.f));
+          px[s][c] = fmaf(tau, gx, px[s][c]) * rs;
+          py[s][c] = fmaf(tau, gy, py[s][c]) * rs;
+        }
+      } else {
+        // no y-gradient on this row (g_y = 0): the same values with the zero terms dropped
+#pragma unroll
+        for (int c = 0; c < CX; ++c) {
+          const float wr = (c < CX - 1) ? wcur[c + 1] : right;
+          const float gx = BX ? (wr - wcur[c]) * colx[c] : (wr - wcur[c]);
+          const float rs = __builtin_amdgcn_rcpf(fmaf(tau, __builtin_amdgcn_sqrtf(gx * gx), 1.f));
+          px[s][c] = fmaf(tau, gx, px[s][c]) * rs;
+          py[s][c] = py[s][c] * rs;
+        }
       }
 #pragma unroll
       for (int c = 0; c < CX; ++c) wcur[c] = wnext[c];
@@ -152,18 +219,29 @@ __device__ __forceinline__ void tv_tile_impl(const TvLaunch& a, const int k, con
 
   // epilogue: interior pixels only
   const int tc0 = L * CX;
+  uint32_t rows_out = 0;  // bit s: row r0 + s is an interior row of this tile inside the image
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int tr = k * S + s, gr = r0 + s;
+    rows_out |= (tr >= a.halo && tr < a.halo + a.IY && gr < a.H) ? (1u << s) : 0u;
+  }
+  rows_out = __builtin_amdgcn_readfirstlane(rows_out);
+  auto col_out = [&](int c) {
+    const int tcc = tc0 + c;
+    return tcc >= a.halo && tcc < a.halo + a.IX && c0 + c < a.W;
+  };
   if (a.p_out) {
+    const Rsrc xw = slice_rsrc(a.p_out + base, a.H, a.W);
+    const Rsrc yw = slice_rsrc(a.p_out + a.vol + base, a.H, a.W);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      const int tr = k * S + s, gr = r0 + s;
-      if (tr < a.halo || tr >= a.halo + a.IY || gr >= a.H) continue;
+      if (!((rows_out >> s) & 1u)) continue;
+      const uint32_t ro = row_off(s);
 #pragma unroll
       for (int c = 0; c < CX; ++c) {
-        const int tcc = tc0 + c, gc = c0 + c;
-        if (tcc < a.halo || tcc >= a.halo + a.IX || gc >= a.W) continue;
-        const size_t off = base + (size_t)gr * a.W + gc;
-        a.p_out[off] = px[s][c];
-        a.p_out[a.vol + off] = py[s][c];
+        if (!col_out(c)) continue;
+        st(px[s][c], xw, coff[c], ro);
+        st(py[s][c], yw, coff[c], ro);
       }
     }
     return;
@@ -172,30 +250,42 @@ __device__ __forceinline__ void tv_tile_impl(const TvLaunch& a, const int k, con
   float pyab[CX];
 #pragma unroll
   for (int c = 0; c < CX; ++c) pyab[c] = (k > 0) ? xch[bf][k - 1][0][L * CX + c] : 0.f;
+  // f again (u = f - theta div p needs f itself), all loads in flight together.  The
+  // empty asm hides that this is the slice loaded before the loop, so the compiler
+  // reloads instead of keeping the first loads live through the loop.
+  const float* fe = a.f + base;
+  asm volatile("" : "+s"(fe));
+  const Rsrc fr2 = slice_rsrc(fe, a.H, a.W);
+  float fv[S][CX];
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const uint32_t ro = row_off(s);
+#pragma unroll
+    for (int c = 0; c < CX; ++c) fv[s][c] = ld(fr2, coff[c], ro);
+  }
+  const Rsrc uw = slice_rsrc(a.u + base, a.H, a.W);
+  const Rsrc dw = slice_rsrc(a.d_out ? a.d_out + base : a.u + base, a.H, a.W);
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const float left = from_left(px[s][CX - 1]);
-    const int tr = k * S + s, gr = r0 + s;
-    const bool rowok = tr >= a.halo && tr < a.halo + a.IY && gr < a.H;
+    if (!((rows_out >> s) & 1u)) continue;
+    const uint32_t ro = row_off(s);
 #pragma unroll
     for (int c = 0; c < CX; ++c) {
       const float pxl = (c > 0) ? px[s][c - 1] : left;
       const float pyu = (s > 0) ? py[s - 1][c] : pyab[c];
       const float dv = (px[s][c] - pxl) + (py[s][c] - pyu);
-      const int tcc = tc0 + c, gc = c0 + c;
-      if (rowok && tcc >= a.halo && tcc < a.halo + a.IX && gc < a.W) {
-        const size_t off = (size_t)gr * a.W + gc;
-        const float fv = fn[off];
-        const float uv = fv - a.theta * dv;
-        a.u[base + off] = uv;
-        if (a.d_out) a.d_out[base + off] = fv - uv;
+      if (col_out(c)) {
+        const float uv = fv[s][c] - a.theta * dv;
+        st(uv, uw, coff[c], ro);
+        if (a.d_out) st(fv[s][c] - uv, dw, coff[c], ro);
       }
     }
   }
 }
 
-// One tile of one slice.  Tiles that lie strictly inside [0, W-1) x [0, H-1) need no
-// boundary masks and take the unmasked code path.
+// One tile of one slice.  Tiles whose columns lie strictly inside [0, W-1) need no
+// x-gradient mask and take the unmasked code path.
 template <int CX, int S, int NW>
 __device__ __forceinline__ void tv_tile(const TvLaunch& a, const int tile, const int slice,
                                         TvExchange<CX, NW>& xch) {
@@ -204,8 +294,8 @@ __device__ __forceinline__ void tv_tile(const TvLaunch& a, const int tile, const
   const int tx = tile % a.tilesX, ty = tile / a.tilesX;
   const size_t base = (size_t)slice * a.H * a.W;
   const int ox = tx * a.IX - a.halo, oy = ty * a.IY - a.halo;
-  const bool interior = ox >= 0 && oy >= 0 && ox + 64 * CX <= a.W - 1 && oy + NW * S <= a.H - 1;
-  if (interior)
+  const bool inner_cols = ox >= 0 && ox + 64 * CX <= a.W - 1;
+  if (inner_cols)
     tv_tile_impl<CX, S, NW, false>(a, k, L, ox, oy, base, xch);
   else
     tv_tile_impl<CX, S, NW, true>(a, k, L, ox, oy, base, xch);
