@@ -27,9 +27,14 @@ HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TFLOPS = 78.6
 # Algorithmic flops of one Chambolle inner iteration per pixel (div 3, w 1,
 # grad 2, |g| 4, 1 + tau|g| 2, p + tau g 4, two divisions 2) and the
-# per-call work (f/theta 1, final div 3, u 2, d 1).
+# per-call work (f/theta 1, final div 3, u 2).  The solve's TV launches read f
+# and write u only (d is formed by the next x-step), and are timed that way.
 TV_FLOPS_PER_PIXEL_ITER = 18
-TV_FLOPS_PER_PIXEL_CALL = 7
+TV_FLOPS_PER_PIXEL_CALL = 6
+# HBM counter record of the TV kernel (rocprofv3 FETCH_SIZE / WRITE_SIZE runs),
+# valid only for the kernel sources it was taken from.
+TV_TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "tv_traffic_512x512x16.json")
+TV_SOURCES = [os.path.join(ROOT, "paper_2511_03093_amd", "csrc", n) for n in ("tv_impl.hpp", "tv.hip")]
 
 
 def parse():
@@ -45,7 +50,35 @@ def parse():
     ap.add_argument("--extra-steps", type=int, default=3)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (HBM counter calibration)")
+    ap.add_argument("--tv-shape", type=int, default=-1,
+                    help="use this TV tile shape instead of autotuning (profiling runs)")
+    ap.add_argument("--xu-block", type=int, default=-1,
+                    help="use this x-update block shape instead of autotuning (profiling runs)")
     return ap.parse_args()
+
+
+def tv_sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for p in TV_SOURCES:
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def tv_traffic(tv_shape, nvox):
+    """HBM bytes per TV launch from the committed counter record, or None when the
+    record is missing, was taken for another shape or size, or predates the sources."""
+    try:
+        with open(TV_TRAFFIC_RECORD) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("sources_sha256") != tv_sources_digest():
+        return None
+    if rec.get("tv_shape") != tv_shape or rec.get("voxels") != nvox:
+        return None
+    return rec["fetch_bytes"] + rec["write_bytes"]
 
 
 def time_launches(fn, reps):
@@ -307,6 +340,9 @@ def main():
     plan = cspnp.Plan(prob.masks, zbc=pd["zbc"], denoiser=pd["denoiser"])
     params = cspnp.params_from(pd)
     tuned = plan.autotune(params)  # launch shapes timed on this device (not part of a step)
+    if a.tv_shape >= 0 or a.xu_block >= 0:
+        plan.set_tuning(a.tv_shape if a.tv_shape >= 0 else tuned[0], a.xu_block if a.xu_block >= 0 else tuned[1])
+        tuned = plan.tuning()
     y = torch.from_numpy(prob.y).cuda()
     u = torch.zeros((NR, H, W), device="cuda")
     d = torch.zeros((NR, H, W), device="cuda")
@@ -344,8 +380,7 @@ def main():
     t_xu = time_launches(lambda: cspnp.cspnp_xupdate(plan._handle, p1, y.data_ptr(), u.data_ptr(), d.data_ptr(),
                                                      None, f.data_ptr(), cspnp._stream()), a.kernel_reps)
     uu = torch.empty_like(u)
-    dd = torch.empty_like(u)
-    t_tv = time_launches(lambda: cspnp.cspnp_denoise(plan._handle, p1, f.data_ptr(), uu.data_ptr(), dd.data_ptr(),
+    t_tv = time_launches(lambda: cspnp.cspnp_denoise(plan._handle, p1, f.data_ptr(), uu.data_ptr(), None,
                                                      None, cspnp._stream()), a.kernel_reps)
     t_fw = time_launches(lambda: cspnp.cspnp_forward(plan._handle, x.data_ptr(), y.data_ptr(), cspnp._stream()),
                          a.kernel_reps)
@@ -358,7 +393,7 @@ def main():
     bits_bytes = R * H * ((W + 31) // 32) * 4
     b_op = nvox * 4 + H * W * 4 + bits_bytes               # read x / write x, y once, bits once
     b_xu = nvox * 12 + H * W * 4 + bits_bytes               # read u, d, write f; y, bits
-    b_tv = nvox * 12                                         # read f, write u, d
+    b_tv = nvox * 8                                          # read f, write u
     tv_flops = nvox * (TV_FLOPS_PER_PIXEL_ITER * pd["tv_inner"] + TV_FLOPS_PER_PIXEL_CALL)
     kernels = {
         "forward": {"us": t_fw * 1e6, "GB/s": b_op / t_fw / 1e9, "hbm_frac": b_op / t_fw / 1e9 / HBM_PEAK_GBS},
@@ -368,9 +403,13 @@ def main():
                     "TFLOP/s": tv_flops / t_tv / 1e12},
     }
     achieved = tv_flops / t_tv / 1e12
-    roofline = {"kernel": "tv_prox (10 fused Chambolle iterations)", "bound": "alu", "achieved": achieved,
-                "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / VALU_PEAK_TFLOPS,
-                "traffic": None}
+    shape = cspnp.cspnp_tv_shape_info(tuned[0])
+    traffic = tv_traffic(tuned[0], nvox)
+    roofline = {"kernel": f"tv_prox: 10 fused Chambolle iterations, tile {shape[0]}x{shape[1]}, {shape[2]} threads",
+                "bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / VALU_PEAK_TFLOPS, "traffic": traffic,
+                "traffic_unit": "bytes per launch (FETCH_SIZE x2 + WRITE_SIZE x1, copy-calibrated)",
+                "algorithmic_bytes": b_tv}
     out = {
         "metric": "voxel-iters/s PnP-ADMM TV+temporal FP32",
         "value": value,
