@@ -88,13 +88,14 @@ template <int CX, int S, int NW>
 __global__ __launch_bounds__(64 * NW) void batch_tv(const TvLaunch* __restrict__ probs, const int4* __restrict__ entries,
                                                     int n, int write_d) {
   __shared__ tvimpl::TvExchange<CX, NW> xch;
+  __shared__ tvimpl::TvStage<CX, S, NW> fst;
   int e, step;
   for (bool ok = next_entry(e, step, n, true); ok; ok = next_entry(e, step, n, false)) {
     const int4 en = entries[e];
     TvLaunch a = probs[en.x];
     if (!write_d) a.d_out = nullptr;
     __syncthreads();  // the previous tile's epilogue has finished reading LDS
-    tvimpl::tv_tile<CX, S, NW>(a, en.y, en.z, xch);
+    tvimpl::tv_tile<CX, S, NW>(a, en.y, en.z, xch, fst);
   }
 }
 

@@ -33,7 +33,8 @@ constexpr int kMaxFused = 16;
 template <int CX, int S, int NW>
 __global__ __launch_bounds__(64 * NW) void tv_kernel(const TvLaunch a) {
   __shared__ tvimpl::TvExchange<CX, NW> xch;
-  tv_tile<CX, S, NW>(a, blockIdx.x, blockIdx.y, xch);
+  __shared__ tvimpl::TvStage<CX, S, NW> fst;
+  tv_tile<CX, S, NW>(a, blockIdx.x, blockIdx.y, xch, fst);
 }
 
 template <int CX, int S, int NW>

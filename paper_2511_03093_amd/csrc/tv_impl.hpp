@@ -55,13 +55,18 @@ __device__ __forceinline__ void st(float v, Rsrc r, uint32_t voff, uint32_t soff
 // so the wave above rebuilds the w of the row below its strip bit for bit.
 template <int CX, int NW>
 using TvExchange = float[2][NW][2][64 * CX];
+// The f values of every lane's S x CX pixels, kept for the epilogue (u = f - theta div p
+// needs f itself, and only f/theta stays in registers).  Lane-private: element (s, c) of
+// lane L in wave k sits at [k][s * CX + c][L], so a wave's accesses are conflict-free.
+template <int CX, int S, int NW>
+using TvStage = float[NW][S * CX][64];
 
 // BX: the tile reaches a column outside [0, W-1), so the x-gradient needs its
 // boundary mask.  Rows without a y-gradient (the last image row, and rows outside
 // the image) are wave-uniform and take a branch of their own.
 template <int CX, int S, int NW, bool BX>
 __device__ __forceinline__ void tv_tile_impl(const TvLaunch& a, const int k, const int L, const int ox, const int oy,
-                                             const size_t base, TvExchange<CX, NW>& xch) {
+                                             const size_t base, TvExchange<CX, NW>& xch, TvStage<CX, S, NW>& fst) {
   // No implicit contraction: a p value must round identically whether its
   // neighbour reads it from a register or through the LDS exchange (the
   // intended fused multiply-adds are written as fmaf).
@@ -120,6 +125,10 @@ __device__ __forceinline__ void tv_tile_impl(const TvLaunch& a, const int k, con
 #pragma unroll
         for (int c = 0; c < CX; ++c) px[s][c] = py[s][c] = 0.f;
     }
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+#pragma unroll
+      for (int c = 0; c < CX; ++c) fst[k][s * CX + c][L] = raw[s][c];
 #pragma unroll
     for (int s = 0; s <= S; ++s) {
       const bool rin = (rows_in >> s) & 1u;
@@ -250,19 +259,11 @@ __device__ __forceinline__ void tv_tile_impl(const TvLaunch& a, const int k, con
   float pyab[CX];
 #pragma unroll
   for (int c = 0; c < CX; ++c) pyab[c] = (k > 0) ? xch[bf][k - 1][0][L * CX + c] : 0.f;
-  // f again (u = f - theta div p needs f itself), all loads in flight together.  The
-  // empty asm hides that this is the slice loaded before the loop, so the compiler
-  // reloads instead of keeping the first loads live through the loop.
-  const float* fe = a.f + base;
-  asm volatile("" : "+s"(fe));
-  const Rsrc fr2 = slice_rsrc(fe, a.H, a.W);
   float fv[S][CX];
 #pragma unroll
-  for (int s = 0; s < S; ++s) {
-    const uint32_t ro = row_off(s);
+  for (int s = 0; s < S; ++s)
 #pragma unroll
-    for (int c = 0; c < CX; ++c) fv[s][c] = ld(fr2, coff[c], ro);
-  }
+    for (int c = 0; c < CX; ++c) fv[s][c] = fst[k][s * CX + c][L];
   const Rsrc uw = slice_rsrc(a.u + base, a.H, a.W);
   const Rsrc dw = slice_rsrc(a.d_out ? a.d_out + base : a.u + base, a.H, a.W);
 #pragma unroll
@@ -288,7 +289,7 @@ __device__ __forceinline__ void tv_tile_impl(const TvLaunch& a, const int k, con
 // x-gradient mask and take the unmasked code path.
 template <int CX, int S, int NW>
 __device__ __forceinline__ void tv_tile(const TvLaunch& a, const int tile, const int slice,
-                                        TvExchange<CX, NW>& xch) {
+                                        TvExchange<CX, NW>& xch, TvStage<CX, S, NW>& fst) {
   const int k = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int L = threadIdx.x & 63;
   const int tx = tile % a.tilesX, ty = tile / a.tilesX;
@@ -296,9 +297,9 @@ __device__ __forceinline__ void tv_tile(const TvLaunch& a, const int tile, const
   const int ox = tx * a.IX - a.halo, oy = ty * a.IY - a.halo;
   const bool inner_cols = ox >= 0 && ox + 64 * CX <= a.W - 1;
   if (inner_cols)
-    tv_tile_impl<CX, S, NW, false>(a, k, L, ox, oy, base, xch);
+    tv_tile_impl<CX, S, NW, false>(a, k, L, ox, oy, base, xch, fst);
   else
-    tv_tile_impl<CX, S, NW, true>(a, k, L, ox, oy, base, xch);
+    tv_tile_impl<CX, S, NW, true>(a, k, L, ox, oy, base, xch, fst);
 }
 
 }  // namespace tvimpl
