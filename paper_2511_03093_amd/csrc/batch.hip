@@ -37,6 +37,15 @@ struct XuProblem {
   int H, W, Wq, pad;
 };
 
+// Pointers read from a problem record are generic; these are device (global)
+// memory, and saying so turns flat accesses into global ones.
+typedef __attribute__((address_space(1))) const float gfloat;
+typedef __attribute__((address_space(1))) float gfloat_w;
+typedef __attribute__((address_space(1))) const uint32_t gword;
+__device__ __forceinline__ const gfloat* to_global(const float* p) { return (const gfloat*)p; }
+__device__ __forceinline__ gfloat_w* to_global(float* p) { return (gfloat_w*)p; }
+__device__ __forceinline__ const gword* to_global(const uint32_t* p) { return (const gword*)p; }
+
 __device__ __forceinline__ bool next_entry(int& e, int& step, int n, bool first) {
   // XCD-aware static schedule over entries [0, n)
   const int G = gridDim.x;
@@ -58,29 +67,37 @@ __global__ __launch_bounds__(kXuThreads) void batch_xupdate(const XuProblem* __r
   int e, step;
   for (bool ok = next_entry(e, step, n, true); ok; ok = next_entry(e, step, n, false)) {
     const int2 en = entries[e];
-    const XuProblem& P = probs[en.x];
+    // the problem record by value: its pointers stay in registers (the stores
+    // below cannot alias them), and the d source is chosen once, so every load
+    // of the pixel is issued before the first is needed
+    const XuProblem P = probs[en.x];
     const int HW = P.H * P.W;
     const int p = en.y * kXuThreads + threadIdx.x;
     if (p >= HW) continue;
     const int h = p / P.W, w = p - h * P.W;
-    const uint32_t m = xuimpl::load_bits<R>(P.bits, P.H, P.Wq, h, w);
-    const double yv = (double)P.y[p];
+    const uint32_t m = xuimpl::load_bits<R, const gword>(to_global(P.bits), P.H, P.Wq, h, w);
+    const double yv = (double)to_global(P.y)[p];
+    const gfloat* __restrict__ us = to_global(P.u);
+    const gfloat* __restrict__ ds = to_global(d_from_f ? P.f : P.d);
     double a[R];
     float dv[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const float ur = P.u[(size_t)r * HW + p];
-      dv[r] = d_from_f ? P.f[(size_t)r * HW + p] - ur : P.d[(size_t)r * HW + p];
+      const float ur = us[(size_t)r * HW + p];
+      const float dr = ds[(size_t)r * HW + p];
+      dv[r] = d_from_f ? dr - ur : dr;
       a[r] = P.z.rho * ((double)ur - (double)dv[r]);
       if ((m >> r) & 1u) a[r] += yv;
     }
     xuimpl::pixel_solve<R>(P.z, m, a);
     if (emit_x) {
+      gfloat_w* xo = to_global(P.x);
 #pragma unroll
-      for (int r = 0; r < R; ++r) P.x[(size_t)r * HW + p] = (float)a[r];
+      for (int r = 0; r < R; ++r) xo[(size_t)r * HW + p] = (float)a[r];
     }
+    gfloat_w* fo = to_global(P.f);
 #pragma unroll
-    for (int r = 0; r < R; ++r) P.f[(size_t)r * HW + p] = (float)(a[r] + (double)dv[r]);
+    for (int r = 0; r < R; ++r) fo[(size_t)r * HW + p] = (float)(a[r] + (double)dv[r]);
   }
 }
 

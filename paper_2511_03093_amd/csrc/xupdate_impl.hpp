@@ -53,9 +53,8 @@ __device__ __forceinline__ void pixel_solve(const ZSolve& z, uint32_t m, double 
   }
 }
 
-template <int R>
-__device__ __forceinline__ uint32_t load_bits(const uint32_t* __restrict__ bits, int H, int Wq,
-                                              int h, int w) {
+template <int R, typename Word = const uint32_t>
+__device__ __forceinline__ uint32_t load_bits(Word* __restrict__ bits, int H, int Wq, int h, int w) {
   uint32_t m = 0;
 #pragma unroll
   for (int r = 0; r < R; ++r) m |= ((bits[((size_t)r * H + h) * Wq + (w >> 5)] >> (w & 31)) & 1u) << r;
