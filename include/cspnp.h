@@ -215,7 +215,10 @@ int cspnp_bm3d_layout(const cspnp_plan* plan, size_t* matches_offset, size_t* co
  * Gradients of <x_bar, x^K>, x^K the last x-step of params->iters iterations
  * started from u = d = 0, with respect to the frames y and the scalars
  * rho, lambda, gamma.  (The paper defines no gradient: this differentiates the
- * iteration this library runs.)  TV (tv_inner <= 16) and Tikhonov denoisers. */
+ * iteration this library runs.)  TV (tv_inner <= 16) and Tikhonov denoisers,
+ * any number of shots N (N > 1 uses the plan's block-elimination scratch, so
+ * the backward of a plan must not overlap another call on the same plan).
+ * Other denoisers: CSPNP_EUNSUPPORTED. */
 
 /* Bytes of the checkpoint buffer: ceil(iters/ckpt_every) x (u, d) volumes. */
 int cspnp_ckpt_size(const cspnp_plan* plan, const cspnp_params* params, int ckpt_every, size_t* bytes);

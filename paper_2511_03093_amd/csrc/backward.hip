@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <vector>
 
+#include "multishot_impl.hpp"
 #include "xupdate_impl.hpp"
 
 namespace cspnp {
@@ -263,6 +264,63 @@ __global__ __launch_bounds__(kThreads) void xupdate_bwd(const ZSolve z, int peri
   if (threadIdx.x == 0) part_gam[blockIdx.x] = s;
 }
 
+// The same for N > 1 shots: lam = A^{-1}(fbar + xbar) by the block elimination
+// (A symmetric), ybar_j += m . lam_j per shot, (L x) over the chain of all N R slices.
+template <int R>
+__global__ __launch_bounds__(kThreads) void xupdate_bwd_ms(int N, double rho, double gamma, int periodic_solve,
+                                                           int periodic_lap, const uint32_t* __restrict__ bits, int H,
+                                                           int W, int Wq, const float* __restrict__ fbar,
+                                                           const float* __restrict__ xbar, const float* __restrict__ uk,
+                                                           const float* __restrict__ dk, const float* __restrict__ fk,
+                                                           float* __restrict__ ybar, float* __restrict__ ubar,
+                                                           float* __restrict__ dbar, double* __restrict__ part_rho,
+                                                           double* __restrict__ part_gam, double* __restrict__ scratch) {
+  const size_t HW = (size_t)H * W;
+  const int NR = N * R;
+  double ar = 0.0, ag = 0.0;
+  for (size_t p = blockIdx.x * (size_t)kThreads + threadIdx.x; p < HW; p += (size_t)gridDim.x * kThreads) {
+    const int h = (int)(p / W), w = (int)(p % W);
+    uint32_t m = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) m |= ((bits[((size_t)r * H + h) * Wq + (w >> 5)] >> (w & 31)) & 1u) << r;
+    auto xval = [&](int g) { return (double)fk[(size_t)g * HW + p] - (double)dk[(size_t)g * HW + p]; };
+    double yb = 0.0;
+    msimpl::solve<R>(
+        m, N, rho, gamma, periodic_solve, HW, p, scratch,
+        [&](int j, int r) {
+          const size_t o = (size_t)(j * R + r) * HW + p;
+          return (double)fbar[o] + (xbar ? (double)xbar[o] : 0.0);
+        },
+        [&](int g, double lam) {
+          const size_t o = (size_t)g * HW + p;
+          const int r = g % R;
+          if ((m >> r) & 1u) yb += lam;
+          if (r == R - 1) {
+            ybar[(size_t)(g / R) * HW + p] += (float)yb;
+            yb = 0.0;
+          }
+          const double xv = xval(g);
+          ar += lam * ((double)uk[o] - (double)dk[o] - xv);
+          double lx;
+          if (NR == 1) {
+            lx = 0.0;
+          } else if (periodic_lap) {
+            lx = 2.0 * xv - xval((g + NR - 1) % NR) - xval((g + 1) % NR);
+          } else {
+            lx = (g > 0 ? xv - xval(g - 1) : 0.0) + (g < NR - 1 ? xv - xval(g + 1) : 0.0);
+          }
+          ag -= lam * lx;
+          ubar[o] = (float)(rho * lam);
+          dbar[o] = (float)((double)fbar[o] - rho * lam);
+        });
+  }
+  double s = block_sum(ar);
+  if (threadIdx.x == 0) part_rho[blockIdx.x] = s;
+  __syncthreads();
+  s = block_sum(ag);
+  if (threadIdx.x == 0) part_gam[blockIdx.x] = s;
+}
+
 // acc[slot] += sum(partial[0..n)) in a fixed order
 __global__ void reduce_into(const double* __restrict__ partial, int n, double* __restrict__ acc, int slot) {
   __shared__ double red[256];
@@ -444,9 +502,16 @@ hipError_t enqueue_backward(const cspnp_plan& pl, const cspnp_params& p, const f
       }
       TRY(AllR::dispatch(de.R, [&](auto rc) {
         constexpr int R = decltype(rc)::value;
-        hipLaunchKernelGGL(xupdate_bwd<R>, G, B, 0, s, zs, periodic_lap, pl.bits, de.H, de.W, pl.Wq, fbar,
-                           k == K - 1 ? xbar : nullptr, V(L.off_seg_u, i), V(L.off_seg_d, i), fk, ybar, ubar, dbar,
-                           part, part + kGrid);
+        if (de.N == 1) {
+          hipLaunchKernelGGL(xupdate_bwd<R>, G, B, 0, s, zs, periodic_lap, pl.bits, de.H, de.W, pl.Wq, fbar,
+                             k == K - 1 ? xbar : nullptr, V(L.off_seg_u, i), V(L.off_seg_d, i), fk, ybar, ubar, dbar,
+                             part, part + kGrid);
+        } else {
+          const int periodic_solve = (periodic_lap && de.N * de.R >= 2 && p.gamma > 0) ? 1 : 0;
+          hipLaunchKernelGGL(xupdate_bwd_ms<R>, G, B, 0, s, de.N, p.rho, p.gamma, periodic_solve, periodic_lap,
+                             pl.bits, de.H, de.W, pl.Wq, fbar, k == K - 1 ? xbar : nullptr, V(L.off_seg_u, i),
+                             V(L.off_seg_d, i), fk, ybar, ubar, dbar, part, part + kGrid, pl.ms_scratch);
+        }
         return hipGetLastError();
       }));
       hipLaunchKernelGGL(reduce_into, dim3(1), dim3(256), 0, s, part, kGrid, acc, 0);
@@ -462,7 +527,6 @@ int validate_diff(const cspnp_plan* plan, const cspnp_params* p, int c) {
   if (int s = validate_plan(plan)) return s;
   if (int s = validate_params(plan, p)) return s;
   if (c < 1) return fail(CSPNP_EINVAL, "ckpt_every must be >= 1");
-  if (plan->desc.N != 1) return fail(CSPNP_EUNSUPPORTED, "the backward is implemented for N = 1 shot");
   if (plan->desc.denoiser == CSPNP_DENOISER_BM3D)
     return fail(CSPNP_EUNSUPPORTED, "the backward is implemented for the TV and Tikhonov denoisers");
   if (plan->desc.denoiser == CSPNP_DENOISER_TV && p->tv_inner > 16)

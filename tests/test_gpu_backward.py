@@ -66,6 +66,23 @@ def test_vjp_matches_oracle(cs, denoiser, zbc, gamma, c):
         assert rel(pbar[2], ref["gamma"]) < 1e-4
 
 
+@pytest.mark.parametrize("N,R,zbc,gamma", [(2, 8, "periodic", 0.1), (3, 4, "neumann", 0.2), (5, 8, "periodic", 0.1),
+                                          (2, 1, "periodic", 0.3)])
+def test_multishot_vjp_matches_oracle(cs, N, R, zbc, gamma):
+    announce("vjp-multishot", N, R, zbc, gamma)
+    prob = synth.make_problem(40, 36, R, N, n_blobs=8, seed=(43, N, R))
+    p = oracle.Params(denoiser="tv", lam=0.05, rho=1.0, gamma=gamma, iters=6, tv_inner=10, zbc=zbc)
+    xbar = np.random.default_rng([44]).normal(size=prob.gt.shape).astype(np.float32)
+    ref = solve_vjp(prob.y, prob.masks, p, xbar.astype(np.float64))
+    plan = cs.Plan(prob.masks, N=N, zbc=zbc, denoiser="tv")
+    x, ybar, pbar = gpu_vjp(cs, plan, cs.params_from(p), to_gpu(prob.y), to_gpu(xbar), 4)
+    assert rel_l2(x, ref["x"]) < 1e-4
+    assert rel_l2(ybar, ref["y"]) < 1e-4
+    assert rel(pbar[0], ref["rho"]) < 1e-4
+    assert rel(pbar[1], ref["lam"]) < 1e-4
+    assert rel(pbar[2], ref["gamma"]) < 1e-4
+
+
 def test_checkpoint_interval_and_determinism(cs):
     announce("ckpt-interval")
     prob = synth.make_problem(64, 72, 8, 1, n_blobs=8, seed=(43,))

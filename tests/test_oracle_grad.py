@@ -79,3 +79,18 @@ def test_vjp_is_linear_in_xbar():
     for k in ("rho", "lam", "gamma"):
         assert abs(gab[k] - (2 * ga[k] - gb[k])) < 1e-10 * (abs(ga[k]) + abs(gb[k]) + 1e-12)
     np.testing.assert_allclose(gab["y"], 2 * ga["y"] - gb["y"], rtol=1e-9, atol=1e-13)
+
+
+@pytest.mark.parametrize("zbc", ["periodic", "neumann"])
+def test_gradient_multishot_matches_complex_step(zbc):
+    # N = 2 shots: the temporal chain couples the two shots' slices
+    prob = make_problem(7, 9, 3, 2, n_blobs=3, seed=(37, len(zbc)))
+    p = oracle.Params(denoiser="tv", lam=0.05, rho=0.9, gamma=0.2, iters=3, tv_inner=4, zbc=zbc)
+    g = mse_grad(prob.y, prob.masks, p, prob.gt)
+    for name in ("rho", "lam", "gamma"):
+        t = getattr(p, name)
+        d = cs_deriv(lambda s: loss_of(prob, p.with_(**{name: s})), t)
+        assert abs(g[name] - d) <= 1e-9 * max(abs(d), 1e-12) + 1e-15
+    v = np.random.default_rng([38]).choice([-1.0, 1.0], size=prob.y.shape)
+    d_y = cs_deriv(lambda t: loss_of(prob, p, prob.y.astype(np.float64) + t * v), 0.0)
+    assert abs(np.sum(g["y"] * v) - d_y) <= 1e-9 * abs(d_y) + 1e-15
