@@ -18,11 +18,15 @@ def _ws(nbytes):
     return t, (t.data_ptr() + 255) & ~255
 
 
+def _scalar(t):
+    return float(t.detach()) if isinstance(t, torch.Tensor) else float(t)
+
+
 class PnPADMM(torch.autograd.Function):
     @staticmethod
     def forward(ctx, y, rho, lam, gamma, plan, settings):
         c = int(settings.get("ckpt_every", 5))
-        p = cspnp.make_params(lam=float(lam), rho=float(rho), gamma=float(gamma), iters=settings["iters"],
+        p = cspnp.make_params(lam=_scalar(lam), rho=_scalar(rho), gamma=_scalar(gamma), iters=settings["iters"],
                               tv_inner=settings.get("tv_inner", 10), tv_tau=settings.get("tv_tau", 0.125))
         y = y.contiguous()
         shape = plan.vol_shape

@@ -44,7 +44,9 @@ def tune(plan, y, x_ref, rho, lam, gamma, iters, steps=20, lr=0.15, tv_inner=10,
         x = pnp_admm(y, r, l, g, plan, iters=iters, tv_inner=tv_inner, ckpt_every=ckpt_every)
         loss = torch.sum((x.double() - x_ref.double()) ** 2) / n
         loss.backward()
-        rec = {"step": s, "loss": float(loss), "rho": float(r), "lam": float(l), "gamma": float(g)}
+        gv = float(g.detach()) if isinstance(g, torch.Tensor) else float(g)
+        rec = {"step": s, "loss": float(loss.detach()), "rho": float(r.detach()), "lam": float(l.detach()),
+               "gamma": gv}
         history.append(rec)
         if best is None or rec["loss"] < best["loss"]:
             best = rec
