@@ -16,9 +16,9 @@
 // the sum of the column sums, without fused multiply-adds -- so they are
 // reproducible exactly.
 //
-// Kernels: bm3d_match (one thread per reference, a 16 x 8 tile of references
-// per workgroup with its search region staged in LDS as FP64, the 15 best
-// candidates kept sorted in registers), bm3d_filter (one wave per group: the
+// Kernels: bm3d_match (one wave per row of 62 references, lane = reference,
+// column sums shared through LDS, the search region of 8 reference rows staged
+// in LDS, the 15 best candidates kept sorted in registers), bm3d_filter (one wave per group: the
 // group's 64 pixels per block across 64 lanes, the 2D DCT through LDS, the
 // Haar transform along the group in registers, FP64 atomic aggregation into
 // numerator/denominator volumes), bm3d_divide_* (division).
@@ -34,11 +34,10 @@ constexpr int kP = 8;
 constexpr int kStep = 3;
 constexpr int kRadius = 19;
 constexpr int kNmax = 16;
-constexpr int kRefTileY = 16;  // references per tile: 16 rows x 8 columns, one thread each
-constexpr int kRefTileX = 8;
-constexpr int kMatchThreads = kRefTileY * kRefTileX;
-constexpr int kRegionH = (kRefTileY - 1) * kStep + kP + 2 * kRadius;  // 91
-constexpr int kRegionW = (kRefTileX - 1) * kStep + kP + 2 * kRadius;  // 67
+constexpr int kMRefs = 62;                                        // references per matching wave
+constexpr int kMWaves = 8;                                        // reference rows per matching workgroup
+constexpr int kMRows = (kMWaves - 1) * kStep + kP + 2 * kRadius;  // 67 region rows
+constexpr int kMCols = 64 * 3 + 2 * kRadius;                      // 230 region columns
 constexpr double kTauHt = 3000.0 / (255.0 * 255.0);
 constexpr double kTauWie = 400.0 / (255.0 * 255.0);
 constexpr double kLambda3d = 2.7;
@@ -47,32 +46,51 @@ constexpr double kLambda3d = 2.7;
 __host__ __device__ inline int ref_count(int n) { return (n - kP) / kStep + 1 + (((n - kP) % kStep) ? 1 : 0); }
 __device__ inline int ref_pos(int i, int n) { return min(i * kStep, n - kP); }
 
+// Block matching, one wave per row of references: lane i is the reference of
+// column index ix0 + i (lanes 62 and 63 hold none and only help with column
+// sums).  For every displacement (dy, dx) in [-19, 19]^2 the wave forms the
+// column sums s(x) = sum_r (a - b)^2 over the block's 8 rows for every column x
+// its references cover -- each lane three consecutive columns, exchanged
+// through LDS -- and a reference's distance is the sum of its 8 column sums in
+// column order.  That is exactly the fixed order a distance is defined with
+// (column sums over rows, then their sum, no fused multiply-add), so sharing
+// column sums between the references of a row changes no rounding.  The
+// workgroup's 8 reference rows and their search region are staged in LDS.
 template <typename T>
-__global__ __launch_bounds__(kMatchThreads) void bm3d_match(const T* __restrict__ img, int H, int W, double tau,
-                                                            int* __restrict__ matches, int* __restrict__ counts) {
+__global__ __launch_bounds__(64 * kMWaves) void bm3d_match(const T* __restrict__ img, int H, int W, double tau,
+                                                           int* __restrict__ matches, int* __restrict__ counts) {
 #pragma clang fp contract(off)
-  __shared__ double reg[kRegionH * kRegionW];
+  __shared__ T reg[kMRows * kMCols];
+  __shared__ double colbuf[kMWaves][64 * 3];
   const int nry = ref_count(H), nrx = ref_count(W);
   const int slice = blockIdx.z;
-  const int iy0 = blockIdx.y * kRefTileY, ix0 = blockIdx.x * kRefTileX;
-  const int oy = max(0, ref_pos(iy0, H) - kRadius), ox = max(0, ref_pos(ix0, W) - kRadius);
-  const int ey = min(H, ref_pos(min(iy0 + kRefTileY - 1, nry - 1), H) + kRadius + kP);
-  const int ex = min(W, ref_pos(min(ix0 + kRefTileX - 1, nrx - 1), W) + kRadius + kP);
-  const int rh = ey - oy, rw = ex - ox;
+  const int iy0 = blockIdx.y * kMWaves, ix0 = blockIdx.x * kMRefs;
+  // first column of lane 0 (the reference position of ix0: 3 ix0, or W - 8 when ix0 is the
+  // last, irregular reference) and the region origin; the region may reach outside the image
+  // and is filled with clamped reads there (never a valid candidate)
+  const int xbase = ref_pos(ix0, W);
+  const int oy = ref_pos(iy0, H) - kRadius, ox = xbase - kRadius;
   const T* __restrict__ im = img + (size_t)slice * H * W;
-  for (int i = threadIdx.x; i < rh * rw; i += kMatchThreads) {
-    const int y = i / rw, x = i - y * rw;
-    reg[y * kRegionW + x] = (double)im[(size_t)(oy + y) * W + (ox + x)];
+  for (int i = threadIdx.x; i < kMRows * kMCols; i += 64 * kMWaves) {
+    const int y = i / kMCols, x = i - y * kMCols;
+    const int gy = min(max(oy + y, 0), H - 1), gx = min(max(ox + x, 0), W - 1);
+    reg[i] = im[(size_t)gy * W + gx];
   }
   __syncthreads();
-  const int iy = iy0 + threadIdx.x / kRefTileX, ix = ix0 + threadIdx.x % kRefTileX;
-  if (iy >= nry || ix >= nrx) return;
-  const int ry = ref_pos(iy, H), rx = ref_pos(ix, W);
-  double ref[kP * kP];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int iy = iy0 + wave;
+  if (iy >= nry) return;  // the whole wave leaves; only wave-level synchronisation follows
+  const int ry = ref_pos(iy, H);
+  const int ix = ix0 + lane;
+  const bool is_ref = lane < kMRefs && ix < nrx;
+  const int rx = is_ref ? ref_pos(ix, W) : xbase;
+  const int k0 = rx - xbase;  // this reference's first column among the wave's columns
+  const int ryl = ry - oy;    // region row of the reference block's first row (19..40)
+  double a[kP][3];
 #pragma unroll
-  for (int r = 0; r < kP; ++r)
+  for (int rr = 0; rr < kP; ++rr)
 #pragma unroll
-    for (int c = 0; c < kP; ++c) ref[r * kP + c] = reg[(ry - oy + r) * kRegionW + (rx - ox + c)];
+    for (int j = 0; j < 3; ++j) a[rr][j] = (double)reg[(ryl + rr) * kMCols + 3 * lane + j + kRadius];
   double bd[kNmax - 1];
   int bi[kNmax - 1];
 #pragma unroll
@@ -80,41 +98,51 @@ __global__ __launch_bounds__(kMatchThreads) void bm3d_match(const T* __restrict_
     bd[k] = INFINITY;
     bi[k] = 0x7fffffff;
   }
-  const int y0 = max(0, ry - kRadius), y1 = min(H - kP, ry + kRadius);
-  const int x0 = max(0, rx - kRadius), x1 = min(W - kP, rx + kRadius);
-  for (int cy = y0; cy <= y1; ++cy) {
-    for (int cx = x0; cx <= x1; ++cx) {
-      if (cy == ry && cx == rx) continue;
-      const double* cand = reg + (cy - oy) * kRegionW + (cx - ox);
-      double acc = 0.0;
+  double* cb = colbuf[wave];
+  for (int dy = -kRadius; dy <= kRadius; ++dy) {
+    const int cy = ry + dy;
+    if (cy < 0 || cy > H - kP) continue;  // wave-uniform: no reference of the row has this candidate row
+    const T* crow = reg + (ryl + dy) * kMCols + 3 * lane + kRadius;
+    for (int dx = -kRadius; dx <= kRadius; ++dx) {
 #pragma unroll
-      for (int c = 0; c < kP; ++c) {
+      for (int j = 0; j < 3; ++j) {
         double col = 0.0;
 #pragma unroll
-        for (int r = 0; r < kP; ++r) {
-          const double t = ref[r * kP + c] - cand[r * kRegionW + c];
+        for (int rr = 0; rr < kP; ++rr) {
+          const double t = a[rr][j] - (double)crow[rr * kMCols + j + dx];
           col = col + t * t;
         }
-        acc = acc + col;
+        cb[3 * lane + j] = col;
       }
-      const double d = acc * (1.0 / (kP * kP));
-      if (d <= tau && d < bd[kNmax - 2]) {
-        // insertion: walk the (distance, raster index) ordered list, carrying the displaced entry
-        double cd = d;
-        int ci = cy * W + cx;
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      const int cx = rx + dx;
+      if (is_ref && cx >= 0 && cx <= W - kP && (dy != 0 || dx != 0)) {
+        double acc = 0.0;
 #pragma unroll
-        for (int k = 0; k < kNmax - 1; ++k) {
-          const bool better = cd < bd[k] || (cd == bd[k] && ci < bi[k]);
-          const double td = bd[k];
-          const int ti = bi[k];
-          bd[k] = better ? cd : td;
-          bi[k] = better ? ci : ti;
-          cd = better ? td : cd;
-          ci = better ? ti : ci;
+        for (int c = 0; c < kP; ++c) acc = acc + cb[k0 + c];
+        const double d = acc * (1.0 / (kP * kP));
+        if (d <= tau && d < bd[kNmax - 2]) {
+          // insertion: walk the (distance, raster index) ordered list, carrying the displaced entry
+          double cd = d;
+          int ci = cy * W + cx;
+#pragma unroll
+          for (int k = 0; k < kNmax - 1; ++k) {
+            const bool better = cd < bd[k] || (cd == bd[k] && ci < bi[k]);
+            const double td = bd[k];
+            const int ti = bi[k];
+            bd[k] = better ? cd : td;
+            bi[k] = better ? ci : ti;
+            cd = better ? td : cd;
+            ci = better ? ti : ci;
+          }
         }
       }
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     }
   }
+  if (!is_ref) return;
   const size_t g = ((size_t)slice * nry + iy) * nrx + ix;
   int* out = matches + g * kNmax;
   out[0] = ry * W + rx;
@@ -361,7 +389,7 @@ hipError_t launch_bm3d_stages(const cspnp_plan& pl, double sigma, const float* f
   double* basic = reinterpret_cast<double*>(w + L.basic);
   const int nry = ref_count(de.H), nrx = ref_count(de.W);
   const size_t vol = (size_t)NR * de.H * de.W;
-  const dim3 mgrid((nrx + kRefTileX - 1) / kRefTileX, (nry + kRefTileY - 1) / kRefTileY, NR);
+  const dim3 mgrid((nrx + kMRefs - 1) / kMRefs, (nry + kMWaves - 1) / kMWaves, NR);
   FilterArgs fa;
   fa.C = pl.dct;
   fa.sigma = sigma;
@@ -372,7 +400,7 @@ hipError_t launch_bm3d_stages(const cspnp_plan& pl, double sigma, const float* f
   fa.total = NR * nry * nrx;
   const unsigned fblocks = (unsigned)((fa.total + 3) / 4);
   // stage 1
-  hipLaunchKernelGGL(bm3d_match<float>, mgrid, dim3(kMatchThreads), 0, s, f, de.H, de.W, kTauHt, matches, counts);
+  hipLaunchKernelGGL(bm3d_match<float>, mgrid, dim3(64 * kMWaves), 0, s, f, de.H, de.W, kTauHt, matches, counts);
   if (stop_after == 0) return hipGetLastError();
   hipLaunchKernelGGL(fill_zero_d, dim3(1024), dim3(256), 0, s, num, vol);
   hipLaunchKernelGGL(fill_zero_d, dim3(1024), dim3(256), 0, s, den, vol);
@@ -381,7 +409,7 @@ hipError_t launch_bm3d_stages(const cspnp_plan& pl, double sigma, const float* f
   hipLaunchKernelGGL(bm3d_divide_basic, dim3(1024), dim3(256), 0, s, num, den, basic, vol);
   if (stop_after == 1) return hipGetLastError();
   // stage 2
-  hipLaunchKernelGGL(bm3d_match<double>, mgrid, dim3(kMatchThreads), 0, s, basic, de.H, de.W, kTauWie, matches, counts);
+  hipLaunchKernelGGL(bm3d_match<double>, mgrid, dim3(64 * kMWaves), 0, s, basic, de.H, de.W, kTauWie, matches, counts);
   if (stop_after == 2) return hipGetLastError();
   hipLaunchKernelGGL(fill_zero_d, dim3(1024), dim3(256), 0, s, num, vol);
   hipLaunchKernelGGL(fill_zero_d, dim3(1024), dim3(256), 0, s, den, vol);
