@@ -20,8 +20,9 @@
 // column sums shared through LDS, the search region of 8 reference rows staged
 // in LDS, the 15 best candidates kept sorted in registers), bm3d_filter (one wave per group: the
 // group's 64 pixels per block across 64 lanes, the 2D DCT through LDS, the
-// Haar transform along the group in registers, FP64 atomic aggregation into
-// numerator/denominator volumes), bm3d_divide_* (division).
+// Haar transform along the group in registers, aggregation of an 8 x 8 tile of
+// groups into LDS with FP64 atomics, then once per pixel into the numerator and
+// denominator volumes), bm3d_divide_* (division).
 #include <cmath>
 
 #include "common.hpp"
@@ -38,6 +39,9 @@ constexpr int kMRefs = 62;                                        // references 
 constexpr int kMWaves = 8;                                        // reference rows per matching workgroup
 constexpr int kMRows = (kMWaves - 1) * kStep + kP + 2 * kRadius;  // 67 region rows
 constexpr int kMCols = 64 * 3 + 2 * kRadius;                      // 230 region columns
+constexpr int kFTile = 8;                                         // filter workgroup: 8 x 8 references
+constexpr int kFWaves = 8;
+constexpr int kFReg = (kFTile - 1) * kStep + kP + 2 * kRadius;    // 67: the tile's blocks lie in this square
 constexpr double kTauHt = 3000.0 / (255.0 * 255.0);
 constexpr double kTauWie = 400.0 / (255.0 * 255.0);
 constexpr double kLambda3d = 2.7;
@@ -251,77 +255,105 @@ struct FilterArgs {
   const double* C;  // device DCT matrix, C[k*8 + j] = a_k cos(pi (2j+1) k / 16)
   double sigma;
   double thr;  // hard threshold (stage 1)
-  int H, W, nrefs, total;
+  int H, W, nry, nrx;
   int wiener;
 };
 
-// One wave per group.  Stage 1 (wiener = 0): noisy = img.  Stage 2: basic drives the Wiener weights.
-__global__ __launch_bounds__(256) void bm3d_filter(const FilterArgs a, const float* __restrict__ img,
-                                                   const double* __restrict__ basic, const int* __restrict__ matches,
-                                                   const int* __restrict__ counts, double* __restrict__ num,
-                                                   double* __restrict__ den) {
-  __shared__ double lds[4][kNmax * 64];
+// One workgroup per 8 x 8 tile of references, one wave per group (each wave
+// filters eight groups in turn).  Stage 1 (wiener = 0): noisy = img.  Stage 2:
+// basic drives the Wiener weights.  Every block of the tile's groups lies in the
+// 67 x 67 region around the tile (the search window reaches 19 pixels out), so
+// the weighted block estimates are first summed into that region in LDS and the
+// region is then added to the slice's numerator and denominator once per pixel.
+__global__ __launch_bounds__(64 * kFWaves) void bm3d_filter(const FilterArgs a, const float* __restrict__ img,
+                                                            const double* __restrict__ basic,
+                                                            const int* __restrict__ matches,
+                                                            const int* __restrict__ counts, double* __restrict__ num,
+                                                            double* __restrict__ den) {
+  __shared__ double lds[kFWaves][kNmax * 64];
+  __shared__ double accn[kFReg * kFReg];
+  __shared__ double accd[kFReg * kFReg];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int g = blockIdx.x * 4 + wave;
-  if (g >= a.total) return;  // the whole wave leaves; only wave-level synchronisation is used below
-  const int slice = g / a.nrefs;
+  const int slice = blockIdx.z;
+  const int iy0 = blockIdx.y * kFTile, ix0 = blockIdx.x * kFTile;
+  const int oy = ref_pos(iy0, a.H) - kRadius, ox = ref_pos(ix0, a.W) - kRadius;
   const size_t HW = (size_t)a.H * a.W;
-  const int n = counts[g];
-  const int* m = matches + (size_t)g * kNmax;
+  for (int i = threadIdx.x; i < kFReg * kFReg; i += 64 * kFWaves) {
+    accn[i] = 0.0;
+    accd[i] = 0.0;
+  }
+  __syncthreads();
   const int r = lane >> 3, c = lane & 7;
-  int off[kNmax];
-  double v[kNmax], bv[kNmax];
-#pragma unroll
-  for (int b = 0; b < kNmax; ++b) {
-    off[b] = 0;
-    v[b] = 0.0;
-    bv[b] = 0.0;
-    if (b < n) {
-      const int idx = m[b];
-      const int y = idx / a.W, x = idx - y * a.W;
-      off[b] = (y + r) * a.W + (x + c);
-      v[b] = (double)img[slice * HW + off[b]];
-      if (a.wiener) bv[b] = basic[slice * HW + off[b]];
-    }
-  }
   double* buf = lds[wave];
-  dct2<false>(a.C, v, n, buf, lane);
-  haar<false>(v, n);
-  double w;
-  if (!a.wiener) {
-    double kept = 0.0;
+  for (int k = wave; k < kFTile * kFTile; k += kFWaves) {
+    const int iy = iy0 + k / kFTile, ix = ix0 + k % kFTile;
+    if (iy >= a.nry || ix >= a.nrx) continue;  // wave-uniform
+    const size_t g = ((size_t)slice * a.nry + iy) * a.nrx + ix;
+    const int n = counts[g];
+    const int* m = matches + g * kNmax;
+    int off[kNmax];
+    double v[kNmax], bv[kNmax];
 #pragma unroll
-    for (int b = 0; b < kNmax; ++b)
+    for (int b = 0; b < kNmax; ++b) {
+      off[b] = 0;
+      v[b] = 0.0;
+      bv[b] = 0.0;
       if (b < n) {
-        if (fabs(v[b]) >= a.thr) kept += 1.0;
-        else v[b] = 0.0;
+        const int idx = m[b];
+        const int y = idx / a.W, x = idx - y * a.W;
+        const int o = (y + r) * a.W + (x + c);
+        off[b] = (y + r - oy) * kFReg + (x + c - ox);
+        v[b] = (double)img[slice * HW + o];
+        if (a.wiener) bv[b] = basic[slice * HW + o];
       }
-    kept = wave_sum(kept);
-    w = 1.0 / (a.sigma * a.sigma * fmax(1.0, kept));
-  } else {
-    dct2<false>(a.C, bv, n, buf, lane);
-    haar<false>(bv, n);
-    double wn = 0.0;
-    const double s2 = a.sigma * a.sigma;
-#pragma unroll
-    for (int b = 0; b < kNmax; ++b)
-      if (b < n) {
-        const double bb = bv[b] * bv[b];
-        const double wc = bb / (bb + s2);
-        v[b] *= wc;
-        wn += wc * wc;
-      }
-    wn = wave_sum(wn);
-    w = 1.0 / (s2 * (wn > 0.0 ? wn : 1.0));
-  }
-  haar<true>(v, n);
-  dct2<true>(a.C, v, n, buf, lane);
-#pragma unroll
-  for (int b = 0; b < kNmax; ++b)
-    if (b < n) {
-      unsafeAtomicAdd(num + slice * HW + off[b], w * v[b]);
-      unsafeAtomicAdd(den + slice * HW + off[b], w);
     }
+    dct2<false>(a.C, v, n, buf, lane);
+    haar<false>(v, n);
+    double w;
+    if (!a.wiener) {
+      double kept = 0.0;
+#pragma unroll
+      for (int b = 0; b < kNmax; ++b)
+        if (b < n) {
+          if (fabs(v[b]) >= a.thr) kept += 1.0;
+          else v[b] = 0.0;
+        }
+      kept = wave_sum(kept);
+      w = 1.0 / (a.sigma * a.sigma * fmax(1.0, kept));
+    } else {
+      dct2<false>(a.C, bv, n, buf, lane);
+      haar<false>(bv, n);
+      double wn = 0.0;
+      const double s2 = a.sigma * a.sigma;
+#pragma unroll
+      for (int b = 0; b < kNmax; ++b)
+        if (b < n) {
+          const double bb = bv[b] * bv[b];
+          const double wc = bb / (bb + s2);
+          v[b] *= wc;
+          wn += wc * wc;
+        }
+      wn = wave_sum(wn);
+      w = 1.0 / (s2 * (wn > 0.0 ? wn : 1.0));
+    }
+    haar<true>(v, n);
+    dct2<true>(a.C, v, n, buf, lane);
+#pragma unroll
+    for (int b = 0; b < kNmax; ++b)
+      if (b < n) {
+        atomicAdd(&accn[off[b]], w * v[b]);
+        atomicAdd(&accd[off[b]], w);
+      }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kFReg * kFReg; i += 64 * kFWaves) {
+    const double dv = accd[i];
+    if (dv == 0.0) continue;  // no block of the tile covers this pixel (and none outside the image does)
+    const int y = oy + i / kFReg, x = ox + i % kFReg;
+    const size_t o = slice * HW + (size_t)y * a.W + x;
+    unsafeAtomicAdd(num + o, accn[i]);
+    unsafeAtomicAdd(den + o, dv);
+  }
 }
 
 __global__ __launch_bounds__(256) void fill_zero_d(double* p, size_t n) {
@@ -396,16 +428,16 @@ hipError_t launch_bm3d_stages(const cspnp_plan& pl, double sigma, const float* f
   fa.thr = kLambda3d * sigma;
   fa.H = de.H;
   fa.W = de.W;
-  fa.nrefs = nry * nrx;
-  fa.total = NR * nry * nrx;
-  const unsigned fblocks = (unsigned)((fa.total + 3) / 4);
+  fa.nry = nry;
+  fa.nrx = nrx;
+  const dim3 fgrid((nrx + kFTile - 1) / kFTile, (nry + kFTile - 1) / kFTile, NR);
   // stage 1
   hipLaunchKernelGGL(bm3d_match<float>, mgrid, dim3(64 * kMWaves), 0, s, f, de.H, de.W, kTauHt, matches, counts);
   if (stop_after == 0) return hipGetLastError();
   hipLaunchKernelGGL(fill_zero_d, dim3(1024), dim3(256), 0, s, num, vol);
   hipLaunchKernelGGL(fill_zero_d, dim3(1024), dim3(256), 0, s, den, vol);
   fa.wiener = 0;
-  hipLaunchKernelGGL(bm3d_filter, dim3(fblocks), dim3(256), 0, s, fa, f, nullptr, matches, counts, num, den);
+  hipLaunchKernelGGL(bm3d_filter, fgrid, dim3(64 * kFWaves), 0, s, fa, f, nullptr, matches, counts, num, den);
   hipLaunchKernelGGL(bm3d_divide_basic, dim3(1024), dim3(256), 0, s, num, den, basic, vol);
   if (stop_after == 1) return hipGetLastError();
   // stage 2
@@ -414,7 +446,7 @@ hipError_t launch_bm3d_stages(const cspnp_plan& pl, double sigma, const float* f
   hipLaunchKernelGGL(fill_zero_d, dim3(1024), dim3(256), 0, s, num, vol);
   hipLaunchKernelGGL(fill_zero_d, dim3(1024), dim3(256), 0, s, den, vol);
   fa.wiener = 1;
-  hipLaunchKernelGGL(bm3d_filter, dim3(fblocks), dim3(256), 0, s, fa, f, basic, matches, counts, num, den);
+  hipLaunchKernelGGL(bm3d_filter, fgrid, dim3(64 * kFWaves), 0, s, fa, f, basic, matches, counts, num, den);
   hipLaunchKernelGGL(bm3d_divide_out, dim3(1024), dim3(256), 0, s, num, den, f, u, d_out, vol);
   return hipGetLastError();
 }
