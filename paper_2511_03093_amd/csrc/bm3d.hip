@@ -39,6 +39,8 @@ constexpr int kMRefs = 62;                                        // references 
 constexpr int kMWaves = 8;                                        // reference rows per matching workgroup
 constexpr int kMRows = (kMWaves - 1) * kStep + kP + 2 * kRadius;  // 67 region rows
 constexpr int kMCols = 64 * 3 + 2 * kRadius;                      // 230 region columns
+constexpr int kRowStride = kP + 1;                                // DCT scratch: padded block rows
+constexpr int kBlkStride = kP * kRowStride;
 constexpr int kFTile = 8;                                         // filter workgroup: 8 x 8 references
 constexpr int kFWaves = 8;
 constexpr int kFReg = (kFTile - 1) * kStep + kP + 2 * kRadius;    // 67: the tile's blocks lie in this square
@@ -208,14 +210,23 @@ __device__ __forceinline__ void haar(double (&v)[kNmax], int n) {
 }
 
 // 2D DCT (forward: C X C^T, inverse: C^T X C) of the wave's n blocks; lane = 8*r + c
-// holds pixel (r, c) of every block in v[b].  buf: the wave's LDS scratch [kNmax][64].
+// holds pixel (r, c) of every block in v[b].  buf: the wave's LDS scratch
+// [kNmax][kBlkStride]; rows are padded to 9 doubles so that the eight rows a row
+// pass reads at once fall in distinct LDS banks.
+// The DCT matrix lives in device (global) memory; a pointer read from an
+// argument struct is generic, and generic loads could alias the LDS scratch,
+// which would keep the compiler from hoisting them out of the block loops.
+typedef __attribute__((address_space(1))) const double gdouble;
+
 template <bool INVERSE>
-__device__ __forceinline__ void dct2(const double* __restrict__ C, double (&v)[kNmax], int n, double* buf, int lane) {
+__device__ __forceinline__ void dct2(const double* Cp, double (&v)[kNmax], int n, double* buf, int lane) {
+  const gdouble* __restrict__ C = (const gdouble*)Cp;
   const int r = lane >> 3, c = lane & 7;
+  const int me = r * kRowStride + c;
   // pass 1 along rows: forward Y[r][k=c] = sum_j C[c][j] X[r][j]; inverse Y[r][j=c] = sum_m X[r][m] C[m][c]
 #pragma unroll
   for (int b = 0; b < kNmax; ++b)
-    if (b < n) buf[b * 64 + lane] = v[b];
+    if (b < n) buf[b * kBlkStride + me] = v[b];
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 #pragma unroll
@@ -223,14 +234,15 @@ __device__ __forceinline__ void dct2(const double* __restrict__ C, double (&v)[k
     if (b < n) {
       double s = 0.0;
 #pragma unroll
-      for (int j = 0; j < kP; ++j) s += (INVERSE ? C[j * kP + c] : C[c * kP + j]) * buf[b * 64 + r * kP + j];
+      for (int j = 0; j < kP; ++j)
+        s += (INVERSE ? C[j * kP + c] : C[c * kP + j]) * buf[b * kBlkStride + r * kRowStride + j];
       v[b] = s;
     }
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 #pragma unroll
   for (int b = 0; b < kNmax; ++b)
-    if (b < n) buf[b * 64 + lane] = v[b];
+    if (b < n) buf[b * kBlkStride + me] = v[b];
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   // pass 2 along columns: forward Z[k=r][m=c] = sum_i C[r][i] Y[i][c]; inverse X[i=r][c] = sum_k C[k][r] Y[k][c]
@@ -239,7 +251,8 @@ __device__ __forceinline__ void dct2(const double* __restrict__ C, double (&v)[k
     if (b < n) {
       double s = 0.0;
 #pragma unroll
-      for (int i = 0; i < kP; ++i) s += (INVERSE ? C[i * kP + r] : C[r * kP + i]) * buf[b * 64 + i * kP + c];
+      for (int i = 0; i < kP; ++i)
+        s += (INVERSE ? C[i * kP + r] : C[r * kP + i]) * buf[b * kBlkStride + i * kRowStride + c];
       v[b] = s;
     }
   __builtin_amdgcn_wave_barrier();
@@ -270,7 +283,7 @@ __global__ __launch_bounds__(64 * kFWaves) void bm3d_filter(const FilterArgs a, 
                                                             const int* __restrict__ matches,
                                                             const int* __restrict__ counts, double* __restrict__ num,
                                                             double* __restrict__ den) {
-  __shared__ double lds[kFWaves][kNmax * 64];
+  __shared__ double lds[kFWaves][kNmax * kBlkStride];
   __shared__ double accn[kFReg * kFReg];
   __shared__ double accd[kFReg * kFReg];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
