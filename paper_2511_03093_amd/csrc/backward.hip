@@ -7,12 +7,12 @@
 // segments in reverse; each is recomputed from its checkpoint keeping
 // (u^k, d^k, f^{k+1}), then its iterations are reversed:
 //   d' = f - u', u' = D_theta(f):   fbar = dbar' + D^T(ubar' - dbar')
-//   TV (Chambolle from p = 0): the inner iterates p^t, w^t are rebuilt by the
-//   same arithmetic as the fused forward kernel, then reversed one inner step
-//   at a time:  gbar = (tau/s)(pbar' - (pbar'.p') g/|g|),  wbar = -div gbar,
-//   pbar = pbar'/s - grad wbar,  fbar -= wbar/theta,  thetabar += <wbar, f/theta^2>;
-//   the output step u = f - theta div p^K gives fbar += ubar, pbar^K = theta grad ubar,
-//   thetabar -= <ubar, div p^K>.
+//   TV (Chambolle from p = 0): the fused forward tile writes the inner iterates
+//   p^1..p^K to a tape, and one tile kernel reverses all K inner steps with the
+//   adjoint in registers:  gbar = (tau/s)(pbar' - (pbar'.p') g/|g|),
+//   wbar = -div gbar, pbar = pbar'/s - grad wbar,  fbar -= wbar/theta,
+//   thetabar += <wbar, f/theta^2>; the output step u = f - theta div p^K gives
+//   fbar += ubar, pbar^K = theta grad ubar, thetabar -= <ubar, div p^K>.
 //   x-step x = A^{-1}(m y + rho (u - d)), A symmetric:  lam = A^{-1}(fbar + xbar),
 //   ybar += m.lam, ubar = rho lam, dbar = fbar - rho lam,
 //   rhobar += <lam, u - d - x>, gammabar -= <lam, L x>.
@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "multishot_impl.hpp"
+#include "tv_impl.hpp"
 #include "xupdate_impl.hpp"
 
 namespace cspnp {
@@ -56,139 +57,245 @@ __global__ void zero_doubles(double* p, int n) {
   if (threadIdx.x < n) p[threadIdx.x] = 0.0;
 }
 
-struct Geo {
-  int H, W;
-  size_t HW, vol;
+// ---- reverse of the TV u-step, all inner steps in one tile --------------------
+// One workgroup per (tile, slice); lane L of wave k holds the S x CX pixels of rows
+// k*S.. and columns L*CX.. of the tile.  The adjoint pbar, f/theta and the fbar
+// accumulator stay in registers through all K reverse steps.  Step t reads p^t of
+// the strip's rows -1..S from the tape (p^0 = 0) and recomputes w^t, g, 1/s and
+// p^{t+1} in the forward tile's operation order; two LDS exchanges per step carry
+// the last-row gbar_y of each strip down and the first-row wbar up.  Each step
+// spreads the error of the unknown values beyond the tile one pixel inward and the
+// output step one more, so tiles overlap by K + 1 pixels and write only their
+// interior.  Per step, with p' = (p + tau g)/s:
+//   gbar = (tau/s)(pbar - (pbar.p') g/|g|),  wbar = -div gbar,  pbar <- pbar/s - grad wbar,
+//   fbar -= wbar/theta,  thetabar += <wbar, f/theta^2>;
+// output step u = f - theta div p^K:  fbar = ubar, pbar = theta grad(ubar - dbar),
+//   thetabar -= <ubar - dbar, div p^K>   (fbar starts at dbar + (ubar - dbar)).
+struct TvbArgs {
+  const float* f;     // f^{k+1}, NR*H*W
+  const float* ubar;  // cotangent of u' (of the slice volume)
+  const float* dbar;  // cotangent of d' = f - u'
+  const float* tape;  // px^t at tape + 2 t stride, py^t at tape + (2 t + 1) stride, t = 1..K
+  size_t stride;
+  float* fbar;
+  double* part;  // one FP64 partial of thetabar per workgroup
+  int H, W, tilesX, IX, IY, halo, K;
+  float theta, inv_theta, tau;
 };
 
-__device__ __forceinline__ void coords(const Geo& g, size_t i, int& h, int& w) {
-  const size_t r = i % g.HW;
-  h = (int)(r / g.W);
-  w = (int)(r % g.W);
-}
+constexpr int kTvbCX = 2, kTvbS = 8, kTvbNW = 16;
 
-// w = div p - f/theta (same operation order as the fused forward kernel)
-__global__ __launch_bounds__(kThreads) void tvb_w(Geo g, const float* __restrict__ px, const float* __restrict__ py,
-                                                  const float* __restrict__ f, float inv_theta, float* __restrict__ wo) {
-  for (size_t i = blockIdx.x * (size_t)kThreads + threadIdx.x; i < g.vol; i += (size_t)gridDim.x * kThreads) {
-    int h, w;
-    coords(g, i, h, w);
-    const float pxl = w > 0 ? px[i - 1] : 0.f;
-    const float pyu = h > 0 ? py[i - g.W] : 0.f;
-    const float pxc = w < g.W - 1 ? px[i] : 0.f;
-    const float pyc = h < g.H - 1 ? py[i] : 0.f;
-    wo[i] = (((pxc - pxl) + pyc) - pyu) - __fmul_rn(f[i], inv_theta);
+template <int CX, int S, int NW>
+__global__ __launch_bounds__(64 * NW) void tvb_tile(const TvbArgs a) {
+#pragma clang fp contract(off)
+  using namespace tvimpl;
+  __shared__ float xg[2][NW][64 * CX];  // gbar_y of each strip's last row
+  __shared__ float xw[2][NW][64 * CX];  // wbar of each strip's first row
+  __shared__ double red[NW];
+  const int k = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int L = threadIdx.x & 63;
+  const int tx = blockIdx.x % a.tilesX, ty = blockIdx.x / a.tilesX;
+  const size_t base = (size_t)blockIdx.y * a.H * a.W;
+  const int ox = tx * a.IX - a.halo, oy = ty * a.IY - a.halo;
+  const int c0 = ox + L * CX, r0 = oy + k * S;  // r0 wave-uniform
+
+  uint32_t coff[CX];
+  bool cin[CX], cgx[CX], cxl[CX], cout[CX];
+#pragma unroll
+  for (int c = 0; c < CX; ++c) {
+    const int gc = c0 + c;
+    coff[c] = 4u * (uint32_t)min(max(gc, 0), a.W - 1);
+    cin[c] = gc >= 0 && gc < a.W;
+    cgx[c] = gc >= 0 && gc < a.W - 1;  // the pixel has an x-gradient
+    cxl[c] = gc >= 1 && gc < a.W;      // its left neighbour is in the image
+    const int tcc = L * CX + c;
+    cout[c] = tcc >= a.halo && tcc < a.halo + a.IX && gc < a.W;
   }
-}
+  auto row_off = [&](int s) -> uint32_t { return 4u * (uint32_t)min(max(r0 + s, 0), a.H - 1) * (uint32_t)a.W; };
+  auto rin = [&](int s) { return r0 + s >= 0 && r0 + s < a.H; };
+  auto rgy = [&](int s) { return r0 + s >= 0 && r0 + s < a.H - 1; };
+  auto ryu = [&](int s) { return r0 + s >= 1 && r0 + s < a.H; };
+  auto rout = [&](int s) {
+    const int tr = k * S + s;
+    return tr >= a.halo && tr < a.halo + a.IY && r0 + s < a.H;
+  };
 
-__device__ __forceinline__ void grad_at(const Geo& g, const float* __restrict__ w, size_t i, int h, int x, float& gx,
-                                        float& gy) {
-  const float c = w[i];
-  gx = x < g.W - 1 ? (w[i + 1] - c) : 0.f;
-  gy = h < g.H - 1 ? (w[i + g.W] - c) : 0.f;
-}
-
-// p' = (p + tau grad w) / (1 + tau |grad w|)
-__global__ __launch_bounds__(kThreads) void tvb_p(Geo g, const float* __restrict__ wv, const float* __restrict__ px,
-                                                  const float* __restrict__ py, float tau, float* __restrict__ pxo,
-                                                  float* __restrict__ pyo) {
-  for (size_t i = blockIdx.x * (size_t)kThreads + threadIdx.x; i < g.vol; i += (size_t)gridDim.x * kThreads) {
-    int h, w;
-    coords(g, i, h, w);
-    float gx, gy;
-    grad_at(g, wv, i, h, w, gx, gy);
-    const float q = fmaf(gx, gx, gy * gy);
-    const float rs = __builtin_amdgcn_rcpf(fmaf(tau, __builtin_amdgcn_sqrtf(q), 1.f));
-    pxo[i] = fmaf(tau, gx, px[i]) * rs;
-    pyo[i] = fmaf(tau, gy, py[i]) * rs;
-  }
-}
-
-// output step: ut = ubar - dbar;  fbar = ubar;  pbar = theta grad ut;  thetabar -= <ut, div p^K>
-__global__ __launch_bounds__(kThreads) void tvb_init(Geo g, const float* __restrict__ ubar, const float* __restrict__ dbar,
-                                                     const float* __restrict__ pKx, const float* __restrict__ pKy,
-                                                     float theta, float* __restrict__ fbar, float* __restrict__ pbx,
-                                                     float* __restrict__ pby, double* __restrict__ partial) {
+  const Rsrc fr = slice_rsrc(a.f + base, a.H, a.W);
+  const Rsrc ur = slice_rsrc(a.ubar + base, a.H, a.W);
+  const Rsrc dr = slice_rsrc(a.dbar + base, a.H, a.W);
+  float fs[S + 1][CX], fb[S][CX], bx[S][CX], by[S][CX];
   double acc = 0.0;
-  for (size_t i = blockIdx.x * (size_t)kThreads + threadIdx.x; i < g.vol; i += (size_t)gridDim.x * kThreads) {
-    int h, w;
-    coords(g, i, h, w);
-    const float ut = ubar[i] - dbar[i];
-    fbar[i] = ubar[i];
-    const float utr = w < g.W - 1 ? ubar[i + 1] - dbar[i + 1] : ut;
-    const float utd = h < g.H - 1 ? ubar[i + g.W] - dbar[i + g.W] : ut;
-    pbx[i] = theta * (utr - ut);
-    pby[i] = theta * (utd - ut);
-    const float pxl = w > 0 ? pKx[i - 1] : 0.f;
-    const float pyu = h > 0 ? pKy[i - g.W] : 0.f;
-    const float pxc = w < g.W - 1 ? pKx[i] : 0.f;
-    const float pyc = h < g.H - 1 ? pKy[i] : 0.f;
-    acc -= (double)ut * (double)((pxc - pxl) + (pyc - pyu));
-  }
-  const double s = block_sum(acc);
-  if (threadIdx.x == 0) partial[blockIdx.x] = s;
-}
-
-// reverse of p' = (p + tau g)/s: gbar, and pbar <- pbar/s (in place)
-__global__ __launch_bounds__(kThreads) void tvb_g(Geo g, const float* __restrict__ wv, const float* __restrict__ qx,
-                                                  const float* __restrict__ qy, float tau, float* __restrict__ pbx,
-                                                  float* __restrict__ pby, float* __restrict__ gbx,
-                                                  float* __restrict__ gby) {
-  for (size_t i = blockIdx.x * (size_t)kThreads + threadIdx.x; i < g.vol; i += (size_t)gridDim.x * kThreads) {
-    int h, w;
-    coords(g, i, h, w);
-    float gx, gy;
-    grad_at(g, wv, i, h, w, gx, gy);
-    const float q = fmaf(gx, gx, gy * gy);
-    const float mag = __builtin_amdgcn_sqrtf(q);
-    const float rs = __builtin_amdgcn_rcpf(fmaf(tau, mag, 1.f));
-    const float bx = pbx[i], by = pby[i];
-    const float a = bx * qx[i] + by * qy[i];
-    float nx = 0.f, ny = 0.f;
-    if (mag > 0.f) {
-      const float im = 1.f / mag;
-      nx = gx * im;
-      ny = gy * im;
+  {
+    float ut[S + 1][CX];
+#pragma unroll
+    for (int s = 0; s <= S; ++s) {
+      const uint32_t ro = row_off(s);
+#pragma unroll
+      for (int c = 0; c < CX; ++c) {
+        const float fv = ld(fr, coff[c], ro), uv = ld(ur, coff[c], ro), dv = ld(dr, coff[c], ro);
+        const bool in = rin(s) && cin[c];
+        fs[s][c] = in ? __fmul_rn(fv, a.inv_theta) : 0.f;
+        ut[s][c] = uv - dv;
+        if (s < S) fb[s][c] = uv;
+      }
     }
-    gbx[i] = tau * rs * (bx - a * nx);
-    gby[i] = tau * rs * (by - a * ny);
-    pbx[i] = bx * rs;
-    pby[i] = by * rs;
+    // p^K for the output step's thetabar term
+    const Rsrc kx = slice_rsrc(a.tape + (size_t)(2 * a.K) * a.stride + base, a.H, a.W);
+    const Rsrc ky = slice_rsrc(a.tape + (size_t)(2 * a.K + 1) * a.stride + base, a.H, a.W);
+    float pyu[CX];
+#pragma unroll
+    for (int c = 0; c < CX; ++c) pyu[c] = ryu(0) ? ld(ky, coff[c], row_off(-1)) : 0.f;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const uint32_t ro = row_off(s);
+      float pxs[CX], pys[CX];
+#pragma unroll
+      for (int c = 0; c < CX; ++c) {
+        pxs[c] = ld(kx, coff[c], ro);
+        pys[c] = ld(ky, coff[c], ro);
+      }
+      const float left = from_left(pxs[CX - 1]);
+      const float right = from_right(ut[s][0]);
+#pragma unroll
+      for (int c = 0; c < CX; ++c) {
+        // pbar^K = theta grad(ut), Neumann ends
+        const float utr = (c < CX - 1) ? ut[s][c + 1] : right;
+        bx[s][c] = a.theta * ((cgx[c] ? utr : ut[s][c]) - ut[s][c]);
+        by[s][c] = a.theta * ((rgy(s) ? ut[s + 1][c] : ut[s][c]) - ut[s][c]);
+        const float pxl = cxl[c] ? ((c > 0) ? pxs[c - 1] : left) : 0.f;
+        const float pxc = cgx[c] ? pxs[c] : 0.f;
+        const float pyc = rgy(s) ? pys[c] : 0.f;
+        const float pu = ryu(s) ? pyu[c] : 0.f;
+        if (rout(s) && cout[c]) acc -= (double)ut[s][c] * (double)((pxc - pxl) + (pyc - pu));
+      }
+#pragma unroll
+      for (int c = 0; c < CX; ++c) pyu[c] = pys[c];
+    }
   }
-}
 
-// wbar = -div gbar;  fbar -= wbar/theta;  thetabar += <wbar, f/theta^2>
-__global__ __launch_bounds__(kThreads) void tvb_wbar(Geo g, const float* __restrict__ gbx, const float* __restrict__ gby,
-                                                     const float* __restrict__ f, float theta, float* __restrict__ wbar,
-                                                     float* __restrict__ fbar, double* __restrict__ partial) {
-  double acc = 0.0;
-  const double it2 = 1.0 / ((double)theta * (double)theta);
-  for (size_t i = blockIdx.x * (size_t)kThreads + threadIdx.x; i < g.vol; i += (size_t)gridDim.x * kThreads) {
-    int h, w;
-    coords(g, i, h, w);
-    const float xl = w > 0 ? gbx[i - 1] : 0.f;
-    const float yu = h > 0 ? gby[i - g.W] : 0.f;
-    const float xc = w < g.W - 1 ? gbx[i] : 0.f;
-    const float yc = h < g.H - 1 ? gby[i] : 0.f;
-    const float wb = -((xc - xl) + (yc - yu));
-    wbar[i] = wb;
-    fbar[i] -= wb / theta;
-    acc += (double)wb * (double)f[i] * it2;
+  const float tau = a.tau;
+  const double itheta = 1.0 / (double)a.theta;
+  for (int t = a.K - 1; t >= 0; --t) {
+    const int par = t & 1;
+    // p^t: px on rows 0..S, py on rows -1..S (index +1), zero outside the image
+    float px[S + 1][CX], py[S + 2][CX];
+    if (t > 0) {
+      const Rsrc tx_ = slice_rsrc(a.tape + (size_t)(2 * t) * a.stride + base, a.H, a.W);
+      const Rsrc ty_ = slice_rsrc(a.tape + (size_t)(2 * t + 1) * a.stride + base, a.H, a.W);
+#pragma unroll
+      for (int s = -1; s <= S; ++s) {
+        const uint32_t ro = row_off(s);
+#pragma unroll
+        for (int c = 0; c < CX; ++c) {
+          const bool in = rin(s) && cin[c];
+          if (s >= 0) px[s][c] = in ? ld(tx_, coff[c], ro) : 0.f;
+          py[s + 1][c] = in ? ld(ty_, coff[c], ro) : 0.f;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s <= S + 1; ++s)
+#pragma unroll
+        for (int c = 0; c < CX; ++c) {
+          if (s <= S) px[s][c] = 0.f;
+          py[s][c] = 0.f;
+        }
+    }
+    // w^t on rows 0..S (the forward tile's operation order)
+    float w[S + 1][CX];
+#pragma unroll
+    for (int s = 0; s <= S; ++s) {
+      const float left = from_left(px[s][CX - 1]);
+#pragma unroll
+      for (int c = 0; c < CX; ++c) {
+        const float pxl = (c > 0) ? px[s][c - 1] : left;
+        w[s][c] = (((px[s][c] - pxl) + py[s + 1][c]) - py[s][c]) - fs[s][c];
+      }
+    }
+    // gbar, and pbar <- pbar / s
+    float gbx[S][CX], gby[S][CX];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const float right = from_right(w[s][0]);
+#pragma unroll
+      for (int c = 0; c < CX; ++c) {
+        const float wr = (c < CX - 1) ? w[s][c + 1] : right;
+        const float gx = cgx[c] ? (wr - w[s][c]) : 0.f;
+        const float gy = rgy(s) ? (w[s + 1][c] - w[s][c]) : 0.f;
+        const float q = fmaf(gx, gx, gy * gy);
+        const float mag = __builtin_amdgcn_sqrtf(q);
+        const float rs = __builtin_amdgcn_rcpf(fmaf(tau, mag, 1.f));
+        const float qx = fmaf(tau, gx, px[s][c]) * rs;  // p^{t+1}
+        const float qy = fmaf(tau, gy, py[s + 1][c]) * rs;
+        const float av = bx[s][c] * qx + by[s][c] * qy;
+        float nx = 0.f, ny = 0.f;
+        if (mag > 0.f) {
+          const float im = __builtin_amdgcn_rcpf(mag);
+          nx = gx * im;
+          ny = gy * im;
+        }
+        const float trs = tau * rs;
+        gbx[s][c] = trs * (bx[s][c] - av * nx);
+        gby[s][c] = trs * (by[s][c] - av * ny);
+        bx[s][c] = bx[s][c] * rs;
+        by[s][c] = by[s][c] * rs;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < CX; ++c) xg[par][k][L * CX + c] = gby[S - 1][c];
+    __syncthreads();
+    // wbar = -div gbar;  fbar -= wbar/theta;  thetabar += <wbar, f/theta^2>
+    float wb[S][CX];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const float left = from_left(gbx[s][CX - 1]);
+#pragma unroll
+      for (int c = 0; c < CX; ++c) {
+        const float xl = cxl[c] ? ((c > 0) ? gbx[s][c - 1] : left) : 0.f;
+        const float xc = cgx[c] ? gbx[s][c] : 0.f;
+        const float yc = rgy(s) ? gby[s][c] : 0.f;
+        const float yu = ryu(s) ? ((s > 0) ? gby[s - 1][c] : ((k > 0) ? xg[par][k - 1][L * CX + c] : 0.f)) : 0.f;
+        const float v = -((xc - xl) + (yc - yu));
+        wb[s][c] = v;
+        fb[s][c] = fb[s][c] - v * a.inv_theta;
+        if (rout(s) && cout[c]) acc += (double)v * (double)fs[s][c] * itheta;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < CX; ++c) xw[par][k][L * CX + c] = wb[0][c];
+    __syncthreads();
+    // pbar -= grad wbar
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const float right = from_right(wb[s][0]);
+#pragma unroll
+      for (int c = 0; c < CX; ++c) {
+        const float wr = (c < CX - 1) ? wb[s][c + 1] : right;
+        const float wd = (s < S - 1) ? wb[s + 1][c] : ((k < NW - 1) ? xw[par][k + 1][L * CX + c] : 0.f);
+        const float gx = cgx[c] ? (wr - wb[s][c]) : 0.f;
+        const float gy = rgy(s) ? (wd - wb[s][c]) : 0.f;
+        bx[s][c] = bx[s][c] - gx;
+        by[s][c] = by[s][c] - gy;
+      }
+    }
   }
-  const double s = block_sum(acc);
-  if (threadIdx.x == 0) partial[blockIdx.x] = s;
-}
-
-// pbar -= grad wbar
-__global__ __launch_bounds__(kThreads) void tvb_pbar(Geo g, const float* __restrict__ wbar, float* __restrict__ pbx,
-                                                     float* __restrict__ pby) {
-  for (size_t i = blockIdx.x * (size_t)kThreads + threadIdx.x; i < g.vol; i += (size_t)gridDim.x * kThreads) {
-    int h, w;
-    coords(g, i, h, w);
-    float gx, gy;
-    grad_at(g, wbar, i, h, w, gx, gy);
-    pbx[i] -= gx;
-    pby[i] -= gy;
+  // interior fbar, and the workgroup's thetabar partial (fixed-order reduction)
+  const Rsrc fo = slice_rsrc(a.fbar + base, a.H, a.W);
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    if (!rout(s)) continue;
+    const uint32_t ro = row_off(s);
+#pragma unroll
+    for (int c = 0; c < CX; ++c)
+      if (cout[c]) st(fb[s][c], fo, coff[c], ro);
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+  if (L == 0) red[k] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sum = 0.0;
+    for (int i = 0; i < NW; ++i) sum += red[i];
+    a.part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = sum;
   }
 }
 
@@ -361,6 +468,19 @@ struct RTab {
 using AllR = RTab<1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19, 20, 21, 22, 23, 24, 25, 26, 27,
                   28, 29, 30, 31, 32>;
 
+struct TvbGrid {
+  int halo, IX, IY, tilesX, tiles;
+};
+TvbGrid tvb_grid(int H, int W, int inner) {
+  TvbGrid g;
+  g.halo = inner + 1;
+  g.IX = 64 * kTvbCX - 2 * g.halo;
+  g.IY = kTvbNW * kTvbS - 2 * g.halo;
+  g.tilesX = (W + g.IX - 1) / g.IX;
+  g.tiles = g.tilesX * ((H + g.IY - 1) / g.IY);
+  return g;
+}
+
 // ---- workspace layout -------------------------------------------------------
 
 struct BwdLayout {
@@ -368,10 +488,10 @@ struct BwdLayout {
   int c;      // checkpoint interval
   int inner;  // TV inner iterations (0 for Tikhonov)
   size_t off_seg_u, off_seg_d, off_seg_f;  // c volumes each
-  size_t off_tape_p;                        // (inner+1) x 2 volumes
-  size_t off_tape_w;                        // inner volumes
-  size_t off_adj;                           // ubar, dbar, fbar, pbx, pby, gbx, gby, wbar
-  size_t off_part;                          // 3 x kGrid doubles
+  size_t off_tape_p;                        // (inner+1) x 2 volumes: p^t at 2t, 2t+1 (t >= 1)
+  size_t off_adj;                           // ubar, dbar, fbar
+  size_t off_part;                          // max(3 kGrid, TV tiles) doubles
+  size_t n_part;
   size_t off_acc;                           // 4 doubles
   size_t total;
 };
@@ -387,9 +507,11 @@ BwdLayout bwd_layout(const cspnp_plan& pl, const cspnp_params& p, int c) {
   L.off_seg_d = o; o += (size_t)c * L.vol_bytes;
   L.off_seg_f = o; o += (size_t)c * L.vol_bytes;
   L.off_tape_p = o; o += (size_t)(L.inner + 1) * 2 * L.vol_bytes;
-  L.off_tape_w = o; o += (size_t)L.inner * L.vol_bytes;
-  L.off_adj = o; o += 8 * L.vol_bytes;
-  L.off_part = o; o += align_up(3 * kGrid * sizeof(double));
+  L.off_adj = o; o += 3 * L.vol_bytes;
+  L.n_part = 3 * (size_t)kGrid;
+  if (L.inner > 0)
+    L.n_part = std::max(L.n_part, (size_t)tvb_grid(pl.desc.H, pl.desc.W, L.inner).tiles * pl.desc.N * pl.desc.R);
+  L.off_part = o; o += align_up(L.n_part * sizeof(double));
   L.off_acc = o; o += align_up(4 * sizeof(double));
   // the forward recompute's denoiser workspace (multi-pass TV only)
   o += align_up(tv_workspace_bytes(pl, p.tv_inner));
@@ -427,15 +549,9 @@ hipError_t enqueue_backward(const cspnp_plan& pl, const cspnp_params& p, const f
   float* ubar = V(L.off_adj, 0);
   float* dbar = V(L.off_adj, 1);
   float* fbar = V(L.off_adj, 2);
-  float* pbx = V(L.off_adj, 3);
-  float* pby = V(L.off_adj, 4);
-  float* gbx = V(L.off_adj, 5);
-  float* gby = V(L.off_adj, 6);
-  float* wbar = V(L.off_adj, 7);
   double* part = reinterpret_cast<double*>(ws + L.off_part);
   double* acc = reinterpret_cast<double*>(ws + L.off_acc);
   void* dws = ws + L.off_acc + align_up(4 * sizeof(double));
-  Geo g{de.H, de.W, (size_t)de.H * de.W, vol};
   const ZSolve zs = make_zsolve(de.R, de.zbc, p.rho, p.gamma);
   const int periodic_lap = (de.zbc == CSPNP_ZBC_PERIODIC) ? 1 : 0;
   const double theta = p.lambda / p.rho;
@@ -467,27 +583,31 @@ hipError_t enqueue_backward(const cspnp_plan& pl, const cspnp_params& p, const f
       if (k == K - 1) {
         TRY(launch_fill(fbar, vol, s));  // x^K does not depend on u^K, d^K
       } else if (tv && theta > 0 && L.inner > 0) {
-        // rebuild the TV tape p^0..p^n, w^0..w^{n-1}
-        float* P0x = V(L.off_tape_p, 0);
-        float* P0y = V(L.off_tape_p, 1);
-        TRY(launch_fill(P0x, vol, s));
-        TRY(launch_fill(P0y, vol, s));
-        for (int t = 0; t < L.inner; ++t) {
-          hipLaunchKernelGGL(tvb_w, G, B, 0, s, g, V(L.off_tape_p, 2 * t), V(L.off_tape_p, 2 * t + 1), fk, inv_theta,
-                             V(L.off_tape_w, t));
-          hipLaunchKernelGGL(tvb_p, G, B, 0, s, g, V(L.off_tape_w, t), V(L.off_tape_p, 2 * t), V(L.off_tape_p, 2 * t + 1),
-                             tau, V(L.off_tape_p, 2 * t + 2), V(L.off_tape_p, 2 * t + 3));
-        }
-        hipLaunchKernelGGL(tvb_init, G, B, 0, s, g, ubar, dbar, V(L.off_tape_p, 2 * L.inner),
-                           V(L.off_tape_p, 2 * L.inner + 1), thetaf, fbar, pbx, pby, part);
-        hipLaunchKernelGGL(reduce_into, dim3(1), dim3(256), 0, s, part, kGrid, acc, 3);
-        for (int t = L.inner - 1; t >= 0; --t) {
-          hipLaunchKernelGGL(tvb_g, G, B, 0, s, g, V(L.off_tape_w, t), V(L.off_tape_p, 2 * t + 2),
-                             V(L.off_tape_p, 2 * t + 3), tau, pbx, pby, gbx, gby);
-          hipLaunchKernelGGL(tvb_wbar, G, B, 0, s, g, gbx, gby, fk, thetaf, wbar, fbar, part);
-          hipLaunchKernelGGL(reduce_into, dim3(1), dim3(256), 0, s, part, kGrid, acc, 3);
-          hipLaunchKernelGGL(tvb_pbar, G, B, 0, s, g, wbar, pbx, pby);
-        }
+        // the tape p^1..p^K of this iteration's TV step, then its reverse in one pass
+        float* tape = V(L.off_tape_p, 0);
+        TRY(launch_tv_tape(pl, p.lambda, p.rho, L.inner, p.tv_tau, fk, tape, L.vol_bytes / sizeof(float), s));
+        const TvbGrid tg = tvb_grid(de.H, de.W, L.inner);
+        TvbArgs ta;
+        ta.f = fk;
+        ta.ubar = ubar;
+        ta.dbar = dbar;
+        ta.tape = tape;
+        ta.stride = L.vol_bytes / sizeof(float);
+        ta.fbar = fbar;
+        ta.part = part;
+        ta.H = de.H;
+        ta.W = de.W;
+        ta.tilesX = tg.tilesX;
+        ta.IX = tg.IX;
+        ta.IY = tg.IY;
+        ta.halo = tg.halo;
+        ta.K = L.inner;
+        ta.theta = thetaf;
+        ta.inv_theta = inv_theta;
+        ta.tau = tau;
+        const int nblk = tg.tiles * de.N * de.R;
+        hipLaunchKernelGGL((tvb_tile<kTvbCX, kTvbS, kTvbNW>), dim3(tg.tiles, de.N * de.R), dim3(64 * kTvbNW), 0, s, ta);
+        hipLaunchKernelGGL(reduce_into, dim3(1), dim3(256), 0, s, part, nblk, acc, 3);
         TRY(hipGetLastError());
       } else if (tv) {
         // zero prox weight or no inner iteration: u' = f exactly, fbar = dbar + (ubar - dbar) = ubar

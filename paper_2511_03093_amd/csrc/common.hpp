@@ -146,6 +146,10 @@ hipError_t launch_tikhonov(const cspnp_plan& pl, double lambda, double rho, cons
 // TV prox of every slice of f; ws holds the dual field between passes when
 // the inner iterations do not fit one fused launch.
 size_t tv_workspace_bytes(const cspnp_plan& pl, int tv_inner);
+// p^1..p^K of the Chambolle iteration of every slice of f (from p = 0) into the tape:
+// px^t at tape + 2 t tape_stride, py^t at tape + (2 t + 1) tape_stride; 1 <= K <= 16.
+hipError_t launch_tv_tape(const cspnp_plan& pl, double lambda, double rho, int tv_inner, double tau, const float* f,
+                          float* tape, size_t tape_stride, hipStream_t st);
 hipError_t launch_tv(const cspnp_plan& pl, double lambda, double rho, int tv_inner, double tau,
                      const float* f, float* u, float* d_out, void* ws, hipStream_t s);
 // nslices > 0: denoise only the first nslices slices starting at f/u/d_out (default: all).

@@ -37,6 +37,15 @@ __global__ __launch_bounds__(64 * NW) void tv_kernel(const TvLaunch a) {
   tv_tile<CX, S, NW>(a, blockIdx.x, blockIdx.y, xch, fst);
 }
 
+// The backward's tape: the same tile with p^1..p^K written out (128 x 128 tiles).
+constexpr int kTapeCX = 2, kTapeS = 8, kTapeNW = 16;
+
+__global__ __launch_bounds__(64 * kTapeNW) void tv_tape_kernel(const TvLaunch a) {
+  __shared__ tvimpl::TvExchange<kTapeCX, kTapeNW> xch;
+  __shared__ tvimpl::TvStage<kTapeCX, kTapeS, kTapeNW> fst;
+  tv_tile<kTapeCX, kTapeS, kTapeNW, true>(a, blockIdx.x, blockIdx.y, xch, fst);
+}
+
 template <int CX, int S, int NW>
 hipError_t launch_shape(const TvLaunch& base_args, int NR, hipStream_t st) {
   TvLaunch a = base_args;
@@ -69,6 +78,32 @@ constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 int passes_for(int tv_inner) { return tv_inner <= kMaxFused ? 1 : (tv_inner + kMaxFused - 1) / kMaxFused; }
 
 }  // namespace
+
+hipError_t launch_tv_tape(const cspnp_plan& pl, double lambda, double rho, int tv_inner, double tau, const float* f,
+                          float* tape, size_t tape_stride, hipStream_t st) {
+  const auto& de = pl.desc;
+  const int NR = de.N * de.R;
+  if (tv_inner < 1 || tv_inner > kMaxFused) return hipErrorInvalidValue;
+  TvLaunch a{};
+  a.f = f;
+  a.H = de.H;
+  a.W = de.W;
+  a.vol = (size_t)NR * de.H * de.W;
+  const double theta = lambda / rho;
+  a.theta = (float)theta;
+  a.inv_theta = theta > 0 ? (float)(1.0 / theta) : 0.f;
+  a.tau = (float)tau;
+  a.iters = tv_inner;
+  a.halo = tv_inner;
+  a.tape = tape;
+  a.tape_stride = tape_stride;
+  a.IX = 64 * kTapeCX - 2 * a.halo;
+  a.IY = kTapeNW * kTapeS - 2 * a.halo;
+  a.tilesX = (a.W + a.IX - 1) / a.IX;
+  const int tilesY = (a.H + a.IY - 1) / a.IY;
+  hipLaunchKernelGGL(tv_tape_kernel, dim3(a.tilesX * tilesY, NR), dim3(64 * kTapeNW), 0, st, a);
+  return hipGetLastError();
+}
 
 size_t tv_workspace_bytes(const cspnp_plan& pl, int tv_inner) {
   if (passes_for(tv_inner) <= 1) return 0;

@@ -20,6 +20,12 @@ struct TvLaunch {
   int iters;
   float theta, inv_theta, tau;
   size_t vol;  // NR*H*W
+  // Tape (the backward's record of the inner iterates): when the tape variant of
+  // the tile is instantiated, p^t after inner iteration t = 1..iters is stored at
+  // tape + 2 t tape_stride (px) and tape + (2 t + 1) tape_stride (py), interior
+  // pixels of every tile (so the whole slice), and no u is written.
+  float* tape;
+  size_t tape_stride;
 };
 
 // lane i <- lane i-1 (0 for lane 0)
@@ -64,7 +70,7 @@ using TvStage = float[NW][S * CX][64];
 // BX: the tile reaches a column outside [0, W-1), so the x-gradient needs its
 // boundary mask.  Rows without a y-gradient (the last image row, and rows outside
 // the image) are wave-uniform and take a branch of their own.
-template <int CX, int S, int NW, bool BX>
+template <int CX, int S, int NW, bool BX, bool TAPE = false>
 __device__ __forceinline__ void tv_tile_impl(const TvLaunch& a, const int k, const int L, const int ox, const int oy,
                                              const size_t base, TvExchange<CX, NW>& xch, TvStage<CX, S, NW>& fst) {
   // No implicit contraction: a p value must round identically whether its
@@ -157,6 +163,20 @@ __device__ __forceinline__ void tv_tile_impl(const TvLaunch& a, const int k, con
   }
   __syncthreads();
 
+  // interior pixels (the ones this tile writes)
+  const int tc0 = L * CX;
+  uint32_t rows_out = 0;  // bit s: row r0 + s is an interior row of this tile inside the image
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int tr = k * S + s, gr = r0 + s;
+    rows_out |= (tr >= a.halo && tr < a.halo + a.IY && gr < a.H) ? (1u << s) : 0u;
+  }
+  rows_out = __builtin_amdgcn_readfirstlane(rows_out);
+  auto col_out = [&](int c) {
+    const int tcc = tc0 + c;
+    return tcc >= a.halo && tcc < a.halo + a.IX && c0 + c < a.W;
+  };
+
   const float tau = a.tau;
   for (int it = 0; it < a.iters; ++it) {
     const int b = it & 1;
@@ -214,6 +234,21 @@ __device__ __forceinline__ void tv_tile_impl(const TvLaunch& a, const int k, con
 #pragma unroll
       for (int c = 0; c < CX; ++c) wcur[c] = wnext[c];
     }
+    if constexpr (TAPE) {
+      const Rsrc tx = slice_rsrc(a.tape + (size_t)(2 * (it + 1)) * a.tape_stride + base, a.H, a.W);
+      const Rsrc ty = slice_rsrc(a.tape + (size_t)(2 * (it + 1) + 1) * a.tape_stride + base, a.H, a.W);
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        if (!((rows_out >> s) & 1u)) continue;
+        const uint32_t ro = row_off(s);
+#pragma unroll
+        for (int c = 0; c < CX; ++c) {
+          if (!col_out(c)) continue;
+          st(px[s][c], tx, coff[c], ro);
+          st(py[s][c], ty, coff[c], ro);
+        }
+      }
+    }
     {
       const int nb = b ^ 1;
       const float left = from_left(px[0][CX - 1]);
@@ -225,20 +260,9 @@ __device__ __forceinline__ void tv_tile_impl(const TvLaunch& a, const int k, con
     }
     __syncthreads();
   }
+  if constexpr (TAPE) return;
 
   // epilogue: interior pixels only
-  const int tc0 = L * CX;
-  uint32_t rows_out = 0;  // bit s: row r0 + s is an interior row of this tile inside the image
-#pragma unroll
-  for (int s = 0; s < S; ++s) {
-    const int tr = k * S + s, gr = r0 + s;
-    rows_out |= (tr >= a.halo && tr < a.halo + a.IY && gr < a.H) ? (1u << s) : 0u;
-  }
-  rows_out = __builtin_amdgcn_readfirstlane(rows_out);
-  auto col_out = [&](int c) {
-    const int tcc = tc0 + c;
-    return tcc >= a.halo && tcc < a.halo + a.IX && c0 + c < a.W;
-  };
   if (a.p_out) {
     const Rsrc xw = slice_rsrc(a.p_out + base, a.H, a.W);
     const Rsrc yw = slice_rsrc(a.p_out + a.vol + base, a.H, a.W);
@@ -287,7 +311,7 @@ __device__ __forceinline__ void tv_tile_impl(const TvLaunch& a, const int k, con
 
 // One tile of one slice.  Tiles whose columns lie strictly inside [0, W-1) need no
 // x-gradient mask and take the unmasked code path.
-template <int CX, int S, int NW>
+template <int CX, int S, int NW, bool TAPE = false>
 __device__ __forceinline__ void tv_tile(const TvLaunch& a, const int tile, const int slice,
                                         TvExchange<CX, NW>& xch, TvStage<CX, S, NW>& fst) {
   const int k = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -297,9 +321,9 @@ __device__ __forceinline__ void tv_tile(const TvLaunch& a, const int tile, const
   const int ox = tx * a.IX - a.halo, oy = ty * a.IY - a.halo;
   const bool inner_cols = ox >= 0 && ox + 64 * CX <= a.W - 1;
   if (inner_cols)
-    tv_tile_impl<CX, S, NW, false>(a, k, L, ox, oy, base, xch, fst);
+    tv_tile_impl<CX, S, NW, false, TAPE>(a, k, L, ox, oy, base, xch, fst);
   else
-    tv_tile_impl<CX, S, NW, true>(a, k, L, ox, oy, base, xch, fst);
+    tv_tile_impl<CX, S, NW, true, TAPE>(a, k, L, ox, oy, base, xch, fst);
 }
 
 }  // namespace tvimpl

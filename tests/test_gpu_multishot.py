@@ -83,3 +83,24 @@ def test_psnr_falls_with_compression_ratio(cs):
         x, _, _ = plan.solve(cs.make_params(lam=0.02, rho=1.0, gamma=0.1, iters=60), to_gpu(y))
         scores[R] = M.psnr(to_np(x), gt)
     assert scores[2] > scores[8] > scores[20], scores
+
+
+@pytest.mark.parametrize("N,R,zbc", [(32, 32, "periodic"), (1024, 1, "neumann"), (64, 16, "periodic")])
+def test_maximum_depth(cs, N, R, zbc):
+    """The deepest volume a plan accepts (N*R = 1024 slices): x-step and a short TV solve."""
+    announce("max-depth", N, R, zbc)
+    H, W = 4, 5
+    g = np.random.default_rng([116, N, R])
+    masks = (g.random((R, H, W)) < 0.5).astype(np.uint8)
+    y = (g.random((N, H, W)) * R / 2).astype(np.float32)
+    u = g.random((N * R, H, W)).astype(np.float32)
+    d = (g.normal(size=(N * R, H, W)) * 0.1).astype(np.float32)
+    plan = cs.Plan(masks, N=N, zbc=zbc, denoiser="tv")
+    x, _ = plan.xupdate(cs.make_params(rho=0.5, gamma=0.3), to_gpu(y), to_gpu(u), to_gpu(d))
+    xo = oracle.xstep(y, u, d, masks, 0.5, 0.3, zbc)
+    assert rel_l2(to_np(x), xo) < 1e-6
+    p = oracle.Params(denoiser="tv", lam=0.05, rho=1.0, gamma=0.1, iters=3, tv_inner=5, zbc=zbc)
+    xo, uo, _ = oracle.solve(y, masks, p)
+    xg, ug, _ = plan.solve(cs.params_from(p), to_gpu(y))
+    assert rel_l2(to_np(xg), xo) < 1e-4
+    assert rel_l2(to_np(ug), uo) < 1e-4
