@@ -163,17 +163,19 @@ __device__ __forceinline__ void tv_tile_impl(const TvLaunch& a, const int k, con
   }
   __syncthreads();
 
-  // interior pixels (the ones this tile writes)
-  const int tc0 = L * CX;
-  uint32_t rows_out = 0;  // bit s: row r0 + s is an interior row of this tile inside the image
+  // interior pixels (the ones this tile writes): bit s of interior_rows() is set when
+  // row r0 + s is an interior row of the tile inside the image
+  auto interior_rows = [&]() {
+    uint32_t m = 0;
 #pragma unroll
-  for (int s = 0; s < S; ++s) {
-    const int tr = k * S + s, gr = r0 + s;
-    rows_out |= (tr >= a.halo && tr < a.halo + a.IY && gr < a.H) ? (1u << s) : 0u;
-  }
-  rows_out = __builtin_amdgcn_readfirstlane(rows_out);
+    for (int s = 0; s < S; ++s) {
+      const int tr = k * S + s, gr = r0 + s;
+      m |= (tr >= a.halo && tr < a.halo + a.IY && gr < a.H) ? (1u << s) : 0u;
+    }
+    return __builtin_amdgcn_readfirstlane(m);
+  };
   auto col_out = [&](int c) {
-    const int tcc = tc0 + c;
+    const int tcc = L * CX + c;
     return tcc >= a.halo && tcc < a.halo + a.IX && c0 + c < a.W;
   };
 
@@ -235,6 +237,7 @@ __device__ __forceinline__ void tv_tile_impl(const TvLaunch& a, const int k, con
       for (int c = 0; c < CX; ++c) wcur[c] = wnext[c];
     }
     if constexpr (TAPE) {
+      const uint32_t rows_out = interior_rows();
       const Rsrc tx = slice_rsrc(a.tape + (size_t)(2 * (it + 1)) * a.tape_stride + base, a.H, a.W);
       const Rsrc ty = slice_rsrc(a.tape + (size_t)(2 * (it + 1) + 1) * a.tape_stride + base, a.H, a.W);
 #pragma unroll
@@ -263,6 +266,7 @@ __device__ __forceinline__ void tv_tile_impl(const TvLaunch& a, const int k, con
   if constexpr (TAPE) return;
 
   // epilogue: interior pixels only
+  const uint32_t rows_out = interior_rows();
   if (a.p_out) {
     const Rsrc xw = slice_rsrc(a.p_out + base, a.H, a.W);
     const Rsrc yw = slice_rsrc(a.p_out + a.vol + base, a.H, a.W);
