@@ -7,14 +7,17 @@ namespace cspnp {
 
 namespace {
 
-template <int R>
+// LDS: the forward vectors of a wave's 64 pixels live in LDS ([3][NR][64] doubles)
+// when they fit, else in the plan's HBM scratch volume.
+template <int R, bool LDS>
 __global__ __launch_bounds__(256) void xupdate_multishot(const uint32_t* __restrict__ bits, int H, int W, int Wq,
                                                          int N, double rho, double gamma, int periodic,
                                                          const float* __restrict__ y, const float* __restrict__ u,
                                                          const float* d, int d_from_f, float* __restrict__ x_out,
                                                          float* f_out, double* __restrict__ scratch) {
+  extern __shared__ double lds_scratch[];
   const size_t HW = (size_t)H * W;
-  const size_t p = (size_t)blockIdx.x * 256 + threadIdx.x;
+  const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= HW) return;
   const int h = (int)(p / W), w = (int)(p % W);
   uint32_t m = 0;
@@ -24,22 +27,24 @@ __global__ __launch_bounds__(256) void xupdate_multishot(const uint32_t* __restr
     const float ur = u[g];
     return d_from_f ? d[g] - ur : d[g];
   };
-  msimpl::solve<R>(
-      m, N, rho, gamma, periodic, HW, p, scratch,
-      [&](int j, int r) {
-        const size_t g = (size_t)(j * R + r) * HW + p;
-        const float ur = u[g];
-        const float dr = dual(g);
-        double v = rho * ((double)ur - (double)dr);
-        if ((m >> r) & 1u) v += (double)y[(size_t)j * HW + p];
-        return v;
-      },
-      [&](int g, double xv) {
-        const size_t o = (size_t)g * HW + p;
-        const float dr = dual(o);
-        if (x_out) x_out[o] = (float)xv;
-        if (f_out) f_out[o] = (float)(xv + (double)dr);
-      });
+  auto rhs = [&](int j, int r) {
+    const size_t g = (size_t)(j * R + r) * HW + p;
+    const float ur = u[g];
+    const float dr = dual(g);
+    double v = rho * ((double)ur - (double)dr);
+    if ((m >> r) & 1u) v += (double)y[(size_t)j * HW + p];
+    return v;
+  };
+  auto out = [&](int g, double xv) {
+    const size_t o = (size_t)g * HW + p;
+    const float dr = dual(o);
+    if (x_out) x_out[o] = (float)xv;
+    if (f_out) f_out[o] = (float)(xv + (double)dr);
+  };
+  if constexpr (LDS)
+    msimpl::solve<R>(m, N, rho, gamma, periodic, blockDim.x, threadIdx.x, lds_scratch, rhs, out);
+  else
+    msimpl::solve<R>(m, N, rho, gamma, periodic, HW, p, scratch, rhs, out);
 }
 
 template <int... Rs>
@@ -54,11 +59,18 @@ struct RTab {
 using AllR = RTab<1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19, 20, 21, 22, 23, 24, 25, 26, 27,
                   28, 29, 30, 31, 32>;
 
+constexpr int kLdsLanes = 64;                     // one wave per workgroup on the LDS path
+constexpr size_t kMaxLdsScratch = 80 * 1024;      // N R <= 53: two workgroups per CU
+
 }  // namespace
 
+// The HBM scratch volume: the forward x-step uses it when the LDS block does not fit,
+// the backward's x-step product always.
 size_t multishot_scratch_bytes(const cspnp_desc& de) {
   return de.N > 1 ? 3 * (size_t)de.N * de.R * de.H * de.W * sizeof(double) : 0;
 }
+
+size_t multishot_lds_bytes(const cspnp_desc& de) { return 3 * (size_t)de.N * de.R * kLdsLanes * sizeof(double); }
 
 hipError_t launch_xupdate_multishot(const cspnp_plan& pl, double rho, double gamma, const float* y, const float* u,
                                     const float* d, bool d_from_f, float* x_out, float* f_out, hipStream_t s) {
@@ -66,10 +78,19 @@ hipError_t launch_xupdate_multishot(const cspnp_plan& pl, double rho, double gam
   const int NR = de.N * de.R;
   const int periodic = (de.zbc == CSPNP_ZBC_PERIODIC && NR >= 2 && gamma > 0) ? 1 : 0;
   const size_t HW = (size_t)de.H * de.W;
-  const unsigned blocks = (unsigned)((HW + 255) / 256);
+  const size_t lds = multishot_lds_bytes(de);
   return AllR::dispatch(de.R, [&](auto rc) {
-    hipLaunchKernelGGL(xupdate_multishot<decltype(rc)::value>, dim3(blocks), dim3(256), 0, s, pl.bits, de.H, de.W,
-                       pl.Wq, de.N, rho, gamma, periodic, y, u, d, d_from_f ? 1 : 0, x_out, f_out, pl.ms_scratch);
+    constexpr int R = decltype(rc)::value;
+    if (lds <= kMaxLdsScratch) {
+      // one wave per workgroup, its pixels' forward vectors in LDS
+      hipLaunchKernelGGL((xupdate_multishot<R, true>), dim3((unsigned)((HW + kLdsLanes - 1) / kLdsLanes)),
+                         dim3(kLdsLanes), lds, s, pl.bits, de.H, de.W, pl.Wq, de.N, rho, gamma, periodic, y, u, d,
+                         d_from_f ? 1 : 0, x_out, f_out, nullptr);
+    } else {
+      hipLaunchKernelGGL((xupdate_multishot<R, false>), dim3((unsigned)((HW + 255) / 256)), dim3(256), 0, s, pl.bits,
+                         de.H, de.W, pl.Wq, de.N, rho, gamma, periodic, y, u, d, d_from_f ? 1 : 0, x_out, f_out,
+                         pl.ms_scratch);
+    }
     return hipGetLastError();
   });
 }

@@ -14,7 +14,7 @@
 // sweep stores y_j = S_j^{-1} b~_j and z_j = S_j^{-1} e_R, and the backward sweep
 // is x_j = y_j + gamma x_{j+1,1} z_j.  The wrap is a final Sherman-Morrison step
 // with a second right-hand side w.  Work O(N R) per pixel; the forward vectors
-// live in an FP64 scratch volume of 3 N R H W doubles.
+// live in an FP64 scratch of 3 N R doubles per pixel (LDS or an HBM volume).
 #pragma once
 
 #include "common.hpp"
@@ -33,12 +33,15 @@ __device__ __forceinline__ void thomas(const double (&l)[R], const double (&invd
 
 // rhs(j, r) -> double: entry (j R + r) of the right-hand side.
 // out(g, x) is called once per slice g = 0..NR-1 in order with the solution's entry.
+// scratch: three [NR][stride] double arrays; this pixel's column is q (an HBM volume
+// with stride H W and q the pixel, or an LDS block with stride = threads and q the lane).
 template <int R, typename Rhs, typename Out>
-__device__ __forceinline__ void solve(uint32_t m, int N, double rho, double gamma, int periodic, size_t HW, size_t p,
+__device__ __forceinline__ void solve(uint32_t m, int N, double rho, double gamma, int periodic, size_t stride, size_t q,
                                       double* __restrict__ scratch, Rhs&& rhs, Out&& out) {
   const int NR = N * R;
-  double* Yb = scratch;                    // [NR][HW]
-  double* Zs = scratch + (size_t)NR * HW;  // [NR][HW]
+  const size_t HW = stride, p = q;
+  double* Yb = scratch;                    // [NR][stride]
+  double* Zs = scratch + (size_t)NR * HW;  // [NR][stride]
   double* Yw = scratch + 2 * (size_t)NR * HW;
   double sigma = 0.0, carry_b = 0.0, carry_w = 0.0;
   for (int j = 0; j < N; ++j) {
