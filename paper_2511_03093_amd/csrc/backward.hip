@@ -89,9 +89,15 @@ template <int CX, int S, int NW>
 __global__ __launch_bounds__(64 * NW) void tvb_tile(const TvbArgs a) {
 #pragma clang fp contract(off)
   using namespace tvimpl;
-  __shared__ float xg[2][NW][64 * CX];  // gbar_y of each strip's last row
-  __shared__ float xw[2][NW][64 * CX];  // wbar of each strip's first row
+  // Each exchange buffer is written and read between two barriers that separate it
+  // from its next write, so one copy of each suffices.
+  __shared__ float xg[NW][64 * CX];  // gbar_y of each strip's last row
+  __shared__ float xw[NW][64 * CX];  // wbar of each strip's first row
   __shared__ double red[NW];
+  // per-lane state kept in LDS (each lane reads only what it wrote): f/theta of the
+  // strip rows 0..S and the fbar accumulator
+  __shared__ float fsl[NW][S + 1][64][CX];
+  __shared__ float fbl[NW][S][64][CX];
   const int k = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int L = threadIdx.x & 63;
   const int tx = blockIdx.x % a.tilesX, ty = blockIdx.x / a.tilesX;
@@ -123,7 +129,8 @@ __global__ __launch_bounds__(64 * NW) void tvb_tile(const TvbArgs a) {
   const Rsrc fr = slice_rsrc(a.f + base, a.H, a.W);
   const Rsrc ur = slice_rsrc(a.ubar + base, a.H, a.W);
   const Rsrc dr = slice_rsrc(a.dbar + base, a.H, a.W);
-  float fs[S + 1][CX], fb[S][CX], bx[S][CX], by[S][CX];
+  float bx[S][CX], by[S][CX];
+  auto fs = [&](int s) -> float(&)[CX] { return fsl[k][s][L]; };
   double acc = 0.0;
   {
     float ut[S + 1][CX];
@@ -134,9 +141,9 @@ __global__ __launch_bounds__(64 * NW) void tvb_tile(const TvbArgs a) {
       for (int c = 0; c < CX; ++c) {
         const float fv = ld(fr, coff[c], ro), uv = ld(ur, coff[c], ro), dv = ld(dr, coff[c], ro);
         const bool in = rin(s) && cin[c];
-        fs[s][c] = in ? __fmul_rn(fv, a.inv_theta) : 0.f;
+        fs(s)[c] = in ? __fmul_rn(fv, a.inv_theta) : 0.f;
         ut[s][c] = uv - dv;
-        if (s < S) fb[s][c] = uv;
+        if (s < S) fbl[k][s][L][c] = uv;
       }
     }
     // p^K for the output step's thetabar term
@@ -176,57 +183,71 @@ __global__ __launch_bounds__(64 * NW) void tvb_tile(const TvbArgs a) {
   const float tau = a.tau;
   const double itheta = 1.0 / (double)a.theta;
   for (int t = a.K - 1; t >= 0; --t) {
-    const int par = t & 1;
-    // p^t: px on rows 0..S, py on rows -1..S (index +1), zero outside the image
-    float px[S + 1][CX], py[S + 2][CX];
-    if (t > 0) {
-      const Rsrc tx_ = slice_rsrc(a.tape + (size_t)(2 * t) * a.stride + base, a.H, a.W);
-      const Rsrc ty_ = slice_rsrc(a.tape + (size_t)(2 * t + 1) * a.stride + base, a.H, a.W);
+    // p^t row by row (p^0 = 0; zero outside the image), w^t in the forward tile's
+    // operation order, then gbar and pbar <- pbar / s for each row of the strip
+    const bool tp = t > 0;
+    const Rsrc tx_ = slice_rsrc(a.tape + (size_t)(2 * t) * a.stride + base, a.H, a.W);
+    const Rsrc ty_ = slice_rsrc(a.tape + (size_t)(2 * t + 1) * a.stride + base, a.H, a.W);
+    // all of the step's tape loads are issued first, so their latencies overlap
+    float tpx[S + 1][CX], tpy[S + 2][CX];  // px rows 0..S, py rows -1..S
 #pragma unroll
-      for (int s = -1; s <= S; ++s) {
-        const uint32_t ro = row_off(s);
-#pragma unroll
-        for (int c = 0; c < CX; ++c) {
-          const bool in = rin(s) && cin[c];
-          if (s >= 0) px[s][c] = in ? ld(tx_, coff[c], ro) : 0.f;
-          py[s + 1][c] = in ? ld(ty_, coff[c], ro) : 0.f;
-        }
-      }
-    } else {
-#pragma unroll
-      for (int s = 0; s <= S + 1; ++s)
-#pragma unroll
-        for (int c = 0; c < CX; ++c) {
-          if (s <= S) px[s][c] = 0.f;
-          py[s][c] = 0.f;
-        }
-    }
-    // w^t on rows 0..S (the forward tile's operation order)
-    float w[S + 1][CX];
-#pragma unroll
-    for (int s = 0; s <= S; ++s) {
-      const float left = from_left(px[s][CX - 1]);
+    for (int s = -1; s <= S; ++s) {
+      const uint32_t ro = row_off(s);
 #pragma unroll
       for (int c = 0; c < CX; ++c) {
-        const float pxl = (c > 0) ? px[s][c - 1] : left;
-        w[s][c] = (((px[s][c] - pxl) + py[s + 1][c]) - py[s][c]) - fs[s][c];
+        if (s >= 0) tpx[s][c] = ld(tx_, coff[c], ro);  // in-bounds (clamped); masked below
+        tpy[s + 1][c] = ld(ty_, coff[c], ro);
       }
     }
-    // gbar, and pbar <- pbar / s
+    // keep the loads together (one wait for all of them, not one per row)
+#pragma unroll
+    for (int s = 0; s <= S + 1; ++s)
+#pragma unroll
+      for (int c = 0; c < CX; ++c) {
+        if (s <= S) asm volatile("" : "+v"(tpx[s][c]));
+        asm volatile("" : "+v"(tpy[s][c]));
+      }
+    auto mrow = [&](int s, float& v, int c) { v = (tp && rin(s) && cin[c]) ? v : 0.f; };
+    auto wrow = [&](const float (&pxr)[CX], const float (&pyr)[CX], const float (&pyup)[CX], int s, float (&wr)[CX]) {
+      const float left = from_left(pxr[CX - 1]);
+      float fr_[CX];
+#pragma unroll
+      for (int c = 0; c < CX; ++c) fr_[c] = fs(s)[c];
+#pragma unroll
+      for (int c = 0; c < CX; ++c) {
+        const float pxl = (c > 0) ? pxr[c - 1] : left;
+        wr[c] = (((pxr[c] - pxl) + pyr[c]) - pyup[c]) - fr_[c];
+      }
+    };
+#pragma unroll
+    for (int c = 0; c < CX; ++c) {
+      mrow(-1, tpy[0][c], c);
+      mrow(0, tpx[0][c], c);
+      mrow(0, tpy[1][c], c);
+    }
+    float wc[CX];
+    wrow(tpx[0], tpy[1], tpy[0], 0, wc);
     float gbx[S][CX], gby[S][CX];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      const float right = from_right(w[s][0]);
+      float wn[CX];
 #pragma unroll
       for (int c = 0; c < CX; ++c) {
-        const float wr = (c < CX - 1) ? w[s][c + 1] : right;
-        const float gx = cgx[c] ? (wr - w[s][c]) : 0.f;
-        const float gy = rgy(s) ? (w[s + 1][c] - w[s][c]) : 0.f;
+        mrow(s + 1, tpx[s + 1][c], c);
+        mrow(s + 1, tpy[s + 2][c], c);
+      }
+      wrow(tpx[s + 1], tpy[s + 2], tpy[s + 1], s + 1, wn);
+      const float right = from_right(wc[0]);
+#pragma unroll
+      for (int c = 0; c < CX; ++c) {
+        const float wr = (c < CX - 1) ? wc[c + 1] : right;
+        const float gx = cgx[c] ? (wr - wc[c]) : 0.f;
+        const float gy = rgy(s) ? (wn[c] - wc[c]) : 0.f;
         const float q = fmaf(gx, gx, gy * gy);
         const float mag = __builtin_amdgcn_sqrtf(q);
         const float rs = __builtin_amdgcn_rcpf(fmaf(tau, mag, 1.f));
-        const float qx = fmaf(tau, gx, px[s][c]) * rs;  // p^{t+1}
-        const float qy = fmaf(tau, gy, py[s + 1][c]) * rs;
+        const float qx = fmaf(tau, gx, tpx[s][c]) * rs;  // p^{t+1}
+        const float qy = fmaf(tau, gy, tpy[s + 1][c]) * rs;
         const float av = bx[s][c] * qx + by[s][c] * qy;
         float nx = 0.f, ny = 0.f;
         if (mag > 0.f) {
@@ -240,9 +261,11 @@ __global__ __launch_bounds__(64 * NW) void tvb_tile(const TvbArgs a) {
         bx[s][c] = bx[s][c] * rs;
         by[s][c] = by[s][c] * rs;
       }
+#pragma unroll
+      for (int c = 0; c < CX; ++c) wc[c] = wn[c];
     }
 #pragma unroll
-    for (int c = 0; c < CX; ++c) xg[par][k][L * CX + c] = gby[S - 1][c];
+    for (int c = 0; c < CX; ++c) xg[k][L * CX + c] = gby[S - 1][c];
     __syncthreads();
     // wbar = -div gbar;  fbar -= wbar/theta;  thetabar += <wbar, f/theta^2>
     float wb[S][CX];
@@ -254,15 +277,15 @@ __global__ __launch_bounds__(64 * NW) void tvb_tile(const TvbArgs a) {
         const float xl = cxl[c] ? ((c > 0) ? gbx[s][c - 1] : left) : 0.f;
         const float xc = cgx[c] ? gbx[s][c] : 0.f;
         const float yc = rgy(s) ? gby[s][c] : 0.f;
-        const float yu = ryu(s) ? ((s > 0) ? gby[s - 1][c] : ((k > 0) ? xg[par][k - 1][L * CX + c] : 0.f)) : 0.f;
+        const float yu = ryu(s) ? ((s > 0) ? gby[s - 1][c] : ((k > 0) ? xg[k - 1][L * CX + c] : 0.f)) : 0.f;
         const float v = -((xc - xl) + (yc - yu));
         wb[s][c] = v;
-        fb[s][c] = fb[s][c] - v * a.inv_theta;
-        if (rout(s) && cout[c]) acc += (double)v * (double)fs[s][c] * itheta;
+        fbl[k][s][L][c] = fbl[k][s][L][c] - v * a.inv_theta;
+        if (rout(s) && cout[c]) acc += (double)v * (double)fs(s)[c] * itheta;
       }
     }
 #pragma unroll
-    for (int c = 0; c < CX; ++c) xw[par][k][L * CX + c] = wb[0][c];
+    for (int c = 0; c < CX; ++c) xw[k][L * CX + c] = wb[0][c];
     __syncthreads();
     // pbar -= grad wbar
 #pragma unroll
@@ -271,7 +294,7 @@ __global__ __launch_bounds__(64 * NW) void tvb_tile(const TvbArgs a) {
 #pragma unroll
       for (int c = 0; c < CX; ++c) {
         const float wr = (c < CX - 1) ? wb[s][c + 1] : right;
-        const float wd = (s < S - 1) ? wb[s + 1][c] : ((k < NW - 1) ? xw[par][k + 1][L * CX + c] : 0.f);
+        const float wd = (s < S - 1) ? wb[s + 1][c] : ((k < NW - 1) ? xw[k + 1][L * CX + c] : 0.f);
         const float gx = cgx[c] ? (wr - wb[s][c]) : 0.f;
         const float gy = rgy(s) ? (wd - wb[s][c]) : 0.f;
         bx[s][c] = bx[s][c] - gx;
@@ -287,7 +310,7 @@ __global__ __launch_bounds__(64 * NW) void tvb_tile(const TvbArgs a) {
     const uint32_t ro = row_off(s);
 #pragma unroll
     for (int c = 0; c < CX; ++c)
-      if (cout[c]) st(fb[s][c], fo, coff[c], ro);
+      if (cout[c]) st(fbl[k][s][L][c], fo, coff[c], ro);
   }
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
   if (L == 0) red[k] = acc;
