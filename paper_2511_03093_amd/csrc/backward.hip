@@ -59,8 +59,10 @@ __global__ void zero_doubles(double* p, int n) {
 
 // ---- reverse of the TV u-step, all inner steps in one tile --------------------
 // One workgroup per (tile, slice); lane L of wave k holds the S x CX pixels of rows
-// k*S.. and columns L*CX.. of the tile.  The adjoint pbar, f/theta and the fbar
-// accumulator stay in registers through all K reverse steps.  Step t reads p^t of
+// k*S.. and columns L*CX.. of the tile.  The adjoint pbar stays in registers
+// through all K reverse steps; f/theta and the fbar accumulator sit in LDS (each
+// lane reads back only what it wrote), which keeps the step free of register
+// spills at four waves per SIMD.  Step t reads p^t of
 // the strip's rows -1..S from the tape (p^0 = 0) and recomputes w^t, g, 1/s and
 // p^{t+1} in the forward tile's operation order; two LDS exchanges per step carry
 // the last-row gbar_y of each strip down and the first-row wbar up.  Each step
