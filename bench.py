@@ -81,19 +81,41 @@ def tv_traffic(tv_shape, nvox):
     return rec["fetch_bytes"] + rec["write_bytes"]
 
 
-def time_launches(fn, reps):
-    """Average duration (s) of fn's launches, HIP events on torch's current stream."""
+def time_launches(fn, reps, graph=True):
+    """Average duration (s) of fn's launches, HIP events on torch's current stream.
+
+    With graph=True the reps launches are captured into one graph and the events
+    bracket its replay, so the figure is the kernels' back-to-back duration without
+    the host's per-call launch cost (which exceeds a few-microsecond kernel).  If the
+    capture is refused, the launches are timed eagerly instead.  Returns
+    (seconds per launch, "graph" | "eager").
+    """
     import torch
     fn()
     torch.cuda.synchronize()
     s = torch.cuda.Event(enable_timing=True)
     e = torch.cuda.Event(enable_timing=True)
+    if graph:
+        try:
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                for _ in range(reps):
+                    fn()
+            g.replay()
+            torch.cuda.synchronize()
+            s.record()
+            g.replay()
+            e.record()
+            e.synchronize()
+            return s.elapsed_time(e) / 1e3 / reps, "graph"
+        except Exception:  # noqa: BLE001 - fall back to eager timing
+            torch.cuda.synchronize()
     s.record()
     for _ in range(reps):
         fn()
     e.record()
     e.synchronize()
-    return s.elapsed_time(e) / 1e3 / reps
+    return s.elapsed_time(e) / 1e3 / reps, "eager"
 
 
 def cpu_baseline(prob, p, iters):
@@ -413,14 +435,14 @@ def main():
     f = torch.empty_like(u)
     p1 = cspnp.params_from(pd, iters=1)
     xs = torch.empty_like(u)
-    t_xu = time_launches(lambda: cspnp.cspnp_xupdate(plan._handle, p1, y.data_ptr(), u.data_ptr(), d.data_ptr(),
+    t_xu, mode_xu = time_launches(lambda: cspnp.cspnp_xupdate(plan._handle, p1, y.data_ptr(), u.data_ptr(), d.data_ptr(),
                                                      None, f.data_ptr(), cspnp._stream()), a.kernel_reps)
     uu = torch.empty_like(u)
-    t_tv = time_launches(lambda: cspnp.cspnp_denoise(plan._handle, p1, f.data_ptr(), uu.data_ptr(), None,
+    t_tv, mode_tv = time_launches(lambda: cspnp.cspnp_denoise(plan._handle, p1, f.data_ptr(), uu.data_ptr(), None,
                                                      None, cspnp._stream()), a.kernel_reps)
-    t_fw = time_launches(lambda: cspnp.cspnp_forward(plan._handle, x.data_ptr(), y.data_ptr(), cspnp._stream()),
+    t_fw, mode_fw = time_launches(lambda: cspnp.cspnp_forward(plan._handle, x.data_ptr(), y.data_ptr(), cspnp._stream()),
                          a.kernel_reps)
-    t_adj = time_launches(lambda: cspnp.cspnp_adjoint(plan._handle, y.data_ptr(), xs.data_ptr(), cspnp._stream()),
+    t_adj, mode_adj = time_launches(lambda: cspnp.cspnp_adjoint(plan._handle, y.data_ptr(), xs.data_ptr(), cspnp._stream()),
                           a.kernel_reps)
     # restore y (the forward launches above overwrote it)
     y.copy_(torch.from_numpy(prob.y))
@@ -437,6 +459,8 @@ def main():
         "xupdate": {"us": t_xu * 1e6, "GB/s": b_xu / t_xu / 1e9, "hbm_frac": b_xu / t_xu / 1e9 / HBM_PEAK_GBS},
         "tv_prox": {"us": t_tv * 1e6, "GB/s": b_tv / t_tv / 1e9, "hbm_frac": b_tv / t_tv / 1e9 / HBM_PEAK_GBS,
                     "TFLOP/s": tv_flops / t_tv / 1e12},
+        "timing": {"forward": mode_fw, "adjoint": mode_adj, "xupdate": mode_xu, "tv_prox": mode_tv,
+                   "reps": a.kernel_reps},
     }
     achieved = tv_flops / t_tv / 1e12
     shape = cspnp.cspnp_tv_shape_info(tuned[0])
@@ -473,7 +497,7 @@ def main():
         n = a.copy_probe_mib * (1 << 20) // 4
         src = torch.ones(n, device="cuda")
         dst = torch.empty(n, device="cuda")
-        t_cp = time_launches(lambda: dst.copy_(src), 5)
+        t_cp, _ = time_launches(lambda: dst.copy_(src), 5, graph=False)
         out["copy_probe"] = {"MiB": a.copy_probe_mib, "us": t_cp * 1e6, "GB/s": 2 * n * 4 / t_cp / 1e9}
     if not a.no_extras:
         out["batched"] = batched_vs_plain(a.extra_steps)

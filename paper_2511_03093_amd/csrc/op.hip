@@ -28,7 +28,28 @@ struct Vec<4> {
   }
 };
 
-// y[j][p] = sum_r bit_r(p) * x[j*R + r][p]
+// streaming (nontemporal) stores of the adjoint's output volume; each volume is
+// touched once per launch
+using f4n = float __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void nt_store(float v, float* p) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void nt_store(const float4& v, float* p) {
+  const f4n w = {v.x, v.y, v.z, v.w};
+  __builtin_nontemporal_store(w, reinterpret_cast<f4n*>(p));
+}
+
+// streaming (nontemporal) loads of the forward's input volume
+__device__ __forceinline__ float nt_load(float, const float* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ float4 nt_load(const float4&, const float* p) {
+  const f4n w = __builtin_nontemporal_load(reinterpret_cast<const f4n*>(p));
+  return make_float4(w.x, w.y, w.z, w.w);
+}
+
+// Slices are taken kChunk at a time with every load of a chunk issued before
+// the first is used (slice indices clamped to R - 1, their mask words zeroed),
+// so one wave keeps kChunk loads in flight instead of waiting once per slice.
+constexpr int kChunk = 16;
+
+// y[j][p] = sum_r bit_r(p) * x[j*R + r][p]   (summed in slice order)
 template <int VEC>
 __global__ __launch_bounds__(kOpThreads) void forward_kernel(const float* __restrict__ x,
                                                              float* __restrict__ y,
@@ -44,11 +65,19 @@ __global__ __launch_bounds__(kOpThreads) void forward_kernel(const float* __rest
     float acc[VEC];
 #pragma unroll
     for (int i = 0; i < VEC; ++i) acc[i] = 0.f;
-    for (int r = 0; r < R; ++r) {
-      const uint32_t word = bits[((size_t)r * H + h) * Wq + (w0 >> 5)] >> (w0 & 31);
-      const typename V::T xv = *reinterpret_cast<const typename V::T*>(x + (size_t)(j * R + r) * HW + p);
+    for (int r0 = 0; r0 < R; r0 += kChunk) {
+      uint32_t word[kChunk];
+      typename V::T xv[kChunk];
 #pragma unroll
-      for (int i = 0; i < VEC; ++i) acc[i] += ((word >> i) & 1u) ? V::get(xv, i) : 0.f;
+      for (int q = 0; q < kChunk; ++q) {
+        const int r = min(r0 + q, R - 1);
+        word[q] = r0 + q < R ? bits[((size_t)r * H + h) * Wq + (w0 >> 5)] >> (w0 & 31) : 0u;
+        xv[q] = nt_load(xv[q], x + (size_t)(j * R + r) * HW + p);
+      }
+#pragma unroll
+      for (int q = 0; q < kChunk; ++q)
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) acc[i] += ((word[q] >> i) & 1u) ? V::get(xv[q], i) : 0.f;
     }
     typename V::T out;
 #pragma unroll
@@ -71,12 +100,21 @@ __global__ __launch_bounds__(kOpThreads) void adjoint_kernel(const float* __rest
   const size_t p = (size_t)h * W + w0;
   for (int j = 0; j < N; ++j) {
     const typename V::T yv = *reinterpret_cast<const typename V::T*>(y + (size_t)j * HW + p);
-    for (int r = 0; r < R; ++r) {
-      const uint32_t word = bits[((size_t)r * H + h) * Wq + (w0 >> 5)] >> (w0 & 31);
-      typename V::T out;
+    for (int r0 = 0; r0 < R; r0 += kChunk) {
+      uint32_t word[kChunk];
 #pragma unroll
-      for (int i = 0; i < VEC; ++i) V::set(out, i, ((word >> i) & 1u) ? V::get(yv, i) : 0.f);
-      *reinterpret_cast<typename V::T*>(x + (size_t)(j * R + r) * HW + p) = out;
+      for (int q = 0; q < kChunk; ++q) {
+        const int r = min(r0 + q, R - 1);
+        word[q] = bits[((size_t)r * H + h) * Wq + (w0 >> 5)] >> (w0 & 31);
+      }
+#pragma unroll
+      for (int q = 0; q < kChunk; ++q) {
+        if (r0 + q >= R) break;
+        typename V::T out;
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) V::set(out, i, ((word[q] >> i) & 1u) ? V::get(yv, i) : 0.f);
+        nt_store(out, x + (size_t)(j * R + r0 + q) * HW + p);
+      }
     }
   }
 }
