@@ -56,9 +56,9 @@ __global__ __launch_bounds__(kOpThreads) void forward_kernel(const float* __rest
                                                              const uint32_t* __restrict__ bits,
                                                              int H, int W, int Wq, int R, int N) {
   using V = Vec<VEC>;
-  const int w0 = (blockIdx.x * kOpThreads + threadIdx.x) * VEC;
-  const int h = blockIdx.y;
-  if (w0 >= W) return;
+  const int w0 = (blockIdx.x * blockDim.x + threadIdx.x) * VEC;
+  const int h = blockIdx.y * blockDim.y + threadIdx.y;
+  if (w0 >= W || h >= H) return;
   const size_t HW = (size_t)H * W;
   const size_t p = (size_t)h * W + w0;
   for (int j = 0; j < N; ++j) {
@@ -93,9 +93,9 @@ __global__ __launch_bounds__(kOpThreads) void adjoint_kernel(const float* __rest
                                                              const uint32_t* __restrict__ bits,
                                                              int H, int W, int Wq, int R, int N) {
   using V = Vec<VEC>;
-  const int w0 = (blockIdx.x * kOpThreads + threadIdx.x) * VEC;
-  const int h = blockIdx.y;
-  if (w0 >= W) return;
+  const int w0 = (blockIdx.x * blockDim.x + threadIdx.x) * VEC;
+  const int h = blockIdx.y * blockDim.y + threadIdx.y;
+  if (w0 >= W || h >= H) return;
   const size_t HW = (size_t)H * W;
   const size_t p = (size_t)h * W + w0;
   for (int j = 0; j < N; ++j) {
@@ -124,29 +124,33 @@ bool vec4_ok(int W, const void* a, const void* b) {
          (reinterpret_cast<uintptr_t>(b) % 16 == 0);
 }
 
+// Block = (bx lanes along a row) x (rows): bx covers the row's W/VEC threads rounded up
+// to a wave (at most the whole block), so narrow images do not launch idle lanes.
+dim3 op_block(int W, int vec) {
+  const int need = (W / vec + 63) / 64 * 64;
+  const int bx = need < kOpThreads ? (need > 0 ? need : 64) : kOpThreads;
+  return dim3(bx, kOpThreads / bx);
+}
+
+template <typename K>
+void op_launch(K kernel, const cspnp_plan& pl, const float* in, float* out, hipStream_t s, int vec) {
+  const auto& d = pl.desc;
+  const dim3 block = op_block(d.W, vec);
+  const dim3 grid((d.W / vec + block.x - 1) / block.x, (d.H + block.y - 1) / block.y);
+  hipLaunchKernelGGL(kernel, grid, block, 0, s, in, out, pl.bits, d.H, d.W, pl.Wq, d.R, d.N);
+}
+
 }  // namespace
 
 hipError_t launch_forward(const cspnp_plan& pl, const float* x, float* y, hipStream_t s) {
-  const auto& d = pl.desc;
-  if (vec4_ok(d.W, x, y)) {
-    dim3 grid((d.W / 4 + kOpThreads - 1) / kOpThreads, d.H);
-    hipLaunchKernelGGL(forward_kernel<4>, grid, dim3(kOpThreads), 0, s, x, y, pl.bits, d.H, d.W, pl.Wq, d.R, d.N);
-  } else {
-    dim3 grid((d.W + kOpThreads - 1) / kOpThreads, d.H);
-    hipLaunchKernelGGL(forward_kernel<1>, grid, dim3(kOpThreads), 0, s, x, y, pl.bits, d.H, d.W, pl.Wq, d.R, d.N);
-  }
+  if (vec4_ok(pl.desc.W, x, y)) op_launch(forward_kernel<4>, pl, x, y, s, 4);
+  else op_launch(forward_kernel<1>, pl, x, y, s, 1);
   return hipGetLastError();
 }
 
 hipError_t launch_adjoint(const cspnp_plan& pl, const float* y, float* x, hipStream_t s) {
-  const auto& d = pl.desc;
-  if (vec4_ok(d.W, x, y)) {
-    dim3 grid((d.W / 4 + kOpThreads - 1) / kOpThreads, d.H);
-    hipLaunchKernelGGL(adjoint_kernel<4>, grid, dim3(kOpThreads), 0, s, y, x, pl.bits, d.H, d.W, pl.Wq, d.R, d.N);
-  } else {
-    dim3 grid((d.W + kOpThreads - 1) / kOpThreads, d.H);
-    hipLaunchKernelGGL(adjoint_kernel<1>, grid, dim3(kOpThreads), 0, s, y, x, pl.bits, d.H, d.W, pl.Wq, d.R, d.N);
-  }
+  if (vec4_ok(pl.desc.W, x, y)) op_launch(adjoint_kernel<4>, pl, y, x, s, 4);
+  else op_launch(adjoint_kernel<1>, pl, y, x, s, 1);
   return hipGetLastError();
 }
 
