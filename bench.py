@@ -37,6 +37,9 @@ TV_TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "tv_traffic_512x512x16.json")
 TV_SOURCES = [os.path.join(ROOT, "paper_2511_03093_amd", "csrc", n) for n in ("tv_impl.hpp", "tv.hip")]
 
 
+EXTRAS = ("batched", "differentiable", "bm3d", "paper_schedule", "paper_volume")
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -47,6 +50,8 @@ def parse():
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched (64 snapshots) and differentiable (fwd+bwd) measurements")
+    ap.add_argument("--extras", default=",".join(EXTRAS),
+                    help="comma-separated subset of the extra measurements to run (profiling runs)")
     ap.add_argument("--extra-steps", type=int, default=3)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (HBM counter calibration)")
@@ -382,6 +387,11 @@ def main():
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}); "
               "the multi-GPU sharding is a design note, not an implementation.", file=sys.stderr)
         return 2
+    extras = {e.strip() for e in a.extras.split(",") if e.strip()}
+    unknown = extras - set(EXTRAS)
+    if unknown:
+        print(f"bench.py: unknown --extras entries {sorted(unknown)}; choose from {list(EXTRAS)}", file=sys.stderr)
+        return 2
     import numpy as np
     import torch
 
@@ -500,11 +510,12 @@ def main():
         t_cp, _ = time_launches(lambda: dst.copy_(src), 5, graph=False)
         out["copy_probe"] = {"MiB": a.copy_probe_mib, "us": t_cp * 1e6, "GB/s": 2 * n * 4 / t_cp / 1e9}
     if not a.no_extras:
-        out["batched"] = batched_vs_plain(a.extra_steps)
-        out["differentiable"] = fwd_bwd(a.extra_steps)
-        out["bm3d"] = bm3d_workload(2)
-        out["paper_schedule"] = paper_schedule(a.extra_steps)
-        out["paper_volume"] = paper_volume(a.extra_steps)
+        runs = {"batched": lambda: batched_vs_plain(a.extra_steps), "differentiable": lambda: fwd_bwd(a.extra_steps),
+                "bm3d": lambda: bm3d_workload(2), "paper_schedule": lambda: paper_schedule(a.extra_steps),
+                "paper_volume": lambda: paper_volume(a.extra_steps)}
+        for name in EXTRAS:
+            if name in extras:
+                out[name] = runs[name]()
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, pd, a.cpu_iters)
     print(json.dumps(out), flush=True)

@@ -30,3 +30,11 @@ def test_traffic_record_is_tied_to_the_sources(tmp_path, monkeypatch):
     p.write_text(json.dumps(stale))
     monkeypatch.setattr(bench, "TV_TRAFFIC_RECORD", str(p))
     assert bench.tv_traffic(rec["tv_shape"], rec["voxels"]) is None
+
+
+def test_unknown_extra_is_refused_before_any_gpu_work():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--extras", "differentiable,nope"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "nope" in r.stderr
+    assert r.stdout.strip() == ""
