@@ -376,6 +376,10 @@ def tune_variants(plan, y, gt, starts, iters=100, steps=15):
     return out
 
 
+def progress(msg):
+    print(f"bench.py: {msg}", file=sys.stderr, flush=True)
+
+
 def torch_sync():
     import torch
     torch.cuda.synchronize()
@@ -435,6 +439,7 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = ev0.elapsed_time(ev1) / a.steps
+    progress(f"{a.steps} timed steps: {ms_per_step:.3f} ms per step")
     iters = pd["iters"]
     value = nvox * iters / (ms_per_step / 1e3)
 
@@ -515,9 +520,12 @@ def main():
                 "paper_volume": lambda: paper_volume(a.extra_steps)}
         for name in EXTRAS:
             if name in extras:
+                t_x = time.perf_counter()
                 out[name] = runs[name]()
+                progress(f"extra '{name}' done in {time.perf_counter() - t_x:.1f} s")
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, pd, a.cpu_iters)
+        progress("oracle CPU sample done")
     print(json.dumps(out), flush=True)
     return 0
 
