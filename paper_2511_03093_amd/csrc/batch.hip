@@ -112,7 +112,7 @@ __global__ __launch_bounds__(64 * NW) void batch_tv(const TvLaunch* __restrict__
     TvLaunch a = probs[en.x];
     if (!write_d) a.d_out = nullptr;
     __syncthreads();  // the previous tile's epilogue has finished reading LDS
-    tvimpl::tv_tile<CX, S, NW>(a, en.y, en.z, xch, fst);
+    tvimpl::tv_tile<CX, S, NW, false, true>(a, en.y, en.z, xch, fst);  // p_in is never set here
   }
 }
 

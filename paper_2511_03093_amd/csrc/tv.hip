@@ -30,11 +30,12 @@ using tvimpl::tv_tile;
 
 constexpr int kMaxFused = 16;
 
-template <int CX, int S, int NW>
+// COLD: the launch starts from p = 0 (a single pass, or the first of several).
+template <int CX, int S, int NW, bool COLD>
 __global__ __launch_bounds__(64 * NW) void tv_kernel(const TvLaunch a) {
   __shared__ tvimpl::TvExchange<CX, NW> xch;
   __shared__ tvimpl::TvStage<CX, S, NW> fst;
-  tv_tile<CX, S, NW>(a, blockIdx.x, blockIdx.y, xch, fst);
+  tv_tile<CX, S, NW, false, COLD>(a, blockIdx.x, blockIdx.y, xch, fst);
 }
 
 // The backward's tape: the same tile with p^1..p^K written out (128 x 128 tiles).
@@ -43,7 +44,7 @@ constexpr int kTapeCX = 2, kTapeS = 8, kTapeNW = 16;
 __global__ __launch_bounds__(64 * kTapeNW) void tv_tape_kernel(const TvLaunch a) {
   __shared__ tvimpl::TvExchange<kTapeCX, kTapeNW> xch;
   __shared__ tvimpl::TvStage<kTapeCX, kTapeS, kTapeNW> fst;
-  tv_tile<kTapeCX, kTapeS, kTapeNW, true>(a, blockIdx.x, blockIdx.y, xch, fst);
+  tv_tile<kTapeCX, kTapeS, kTapeNW, true, true>(a, blockIdx.x, blockIdx.y, xch, fst);
 }
 
 template <int CX, int S, int NW>
@@ -56,7 +57,10 @@ hipError_t launch_shape(const TvLaunch& base_args, int NR, hipStream_t st) {
   a.tilesX = (a.W + a.IX - 1) / a.IX;
   const int tilesY = (a.H + a.IY - 1) / a.IY;
   dim3 grid(a.tilesX * tilesY, NR);
-  hipLaunchKernelGGL((tv_kernel<CX, S, NW>), grid, dim3(64 * NW), 0, st, a);
+  if (a.p_in)
+    hipLaunchKernelGGL((tv_kernel<CX, S, NW, false>), grid, dim3(64 * NW), 0, st, a);
+  else
+    hipLaunchKernelGGL((tv_kernel<CX, S, NW, true>), grid, dim3(64 * NW), 0, st, a);
   return hipGetLastError();
 }
 

@@ -70,7 +70,11 @@ using TvStage = float[NW][S * CX][64];
 // BX: the tile reaches a column outside [0, W-1), so the x-gradient needs its
 // boundary mask.  Rows without a y-gradient (the last image row, and rows outside
 // the image) are wave-uniform and take a branch of their own.
-template <int CX, int S, int NW, bool BX, bool TAPE = false>
+// COLD: the launch starts from p = 0 (no p_in).  Every value the first inner
+// iteration exchanges is then +0, so it is published, and the barrier passed,
+// while the tile's loads are still in flight: each wave starts computing as soon
+// as its own rows have arrived.
+template <int CX, int S, int NW, bool BX, bool TAPE = false, bool COLD = false>
 __device__ __forceinline__ void tv_tile_impl(const TvLaunch& a, const int k, const int L, const int ox, const int oy,
                                              const size_t base, TvExchange<CX, NW>& xch, TvStage<CX, S, NW>& fst) {
   // No implicit contraction: a p value must round identically whether its
@@ -113,7 +117,18 @@ __device__ __forceinline__ void tv_tile_impl(const TvLaunch& a, const int k, con
 #pragma unroll
       for (int c = 0; c < CX; ++c) raw[s][c] = ld(fr, coff[c], ro);
     }
-    if (a.p_in) {
+    if constexpr (COLD) {
+#pragma unroll
+      for (int c = 0; c < CX; ++c) {
+        xch[0][k][0][L * CX + c] = 0.f;
+        xch[0][k][1][L * CX + c] = 0.f;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int c = 0; c < CX; ++c) px[s][c] = py[s][c] = 0.f;
+    } else if (a.p_in) {
       const Rsrc xr = slice_rsrc(a.p_in + base, a.H, a.W);
       const Rsrc yr = slice_rsrc(a.p_in + a.vol + base, a.H, a.W);
 #pragma unroll
@@ -147,21 +162,23 @@ __device__ __forceinline__ void tv_tile_impl(const TvLaunch& a, const int k, con
           continue;
         }
         fs[s][c] = v;
-        px[s][c] = in ? px[s][c] : 0.f;
-        py[s][c] = in ? py[s][c] : 0.f;
+        if constexpr (!COLD) {
+          px[s][c] = in ? px[s][c] : 0.f;
+          py[s][c] = in ? py[s][c] : 0.f;
+        }
       }
     }
   }
-  // publish the initial exchange values
-  {
+  if constexpr (!COLD) {
+    // publish the initial exchange values
     const float left = from_left(px[0][CX - 1]);
 #pragma unroll
     for (int c = 0; c < CX; ++c) {
       xch[0][k][0][L * CX + c] = py[S - 1][c];
       xch[0][k][1][L * CX + c] = (px[0][c] - ((c > 0) ? px[0][c - 1] : left)) + py[0][c];
     }
+    __syncthreads();
   }
-  __syncthreads();
 
   // interior pixels (the ones this tile writes): bit s of interior_rows() is set when
   // row r0 + s is an interior row of the tile inside the image
@@ -210,12 +227,18 @@ __device__ __forceinline__ void tv_tile_impl(const TvLaunch& a, const int k, con
 #pragma unroll
         for (int c = 0; c < CX; ++c) wnext[c] = wbl[c];
       }
-      const float right = from_right(wcur[0]);
+      // x-gradients first, for both branches: the last one takes its right
+      // neighbour through a DPP operand of the subtraction itself
+      float gxs[CX];
+#pragma unroll
+      for (int c = 0; c < CX; ++c) {
+        const float d = ((c < CX - 1) ? wcur[c + 1] : from_right(wcur[0])) - wcur[c];
+        gxs[c] = BX ? d * colx[c] : d;
+      }
       if ((rows_gy >> s) & 1u) {
 #pragma unroll
         for (int c = 0; c < CX; ++c) {
-          const float wr = (c < CX - 1) ? wcur[c + 1] : right;
-          const float gx = BX ? (wr - wcur[c]) * colx[c] : (wr - wcur[c]);
+          const float gx = gxs[c];
           const float gy = wnext[c] - wcur[c];
           const float q = fmaf(gx, gx, gy * gy);
           const float rs = __builtin_amdgcn_rcpf(fmaf(tau, __builtin_amdgcn_sqrtf(q), 1.f));
@@ -226,8 +249,7 @@ __device__ __forceinline__ void tv_tile_impl(const TvLaunch& a, const int k, con
         // no y-gradient on this row (g_y = 0): the same values with the zero terms dropped
 #pragma unroll
         for (int c = 0; c < CX; ++c) {
-          const float wr = (c < CX - 1) ? wcur[c + 1] : right;
-          const float gx = BX ? (wr - wcur[c]) * colx[c] : (wr - wcur[c]);
+          const float gx = gxs[c];
           const float rs = __builtin_amdgcn_rcpf(fmaf(tau, __builtin_amdgcn_sqrtf(gx * gx), 1.f));
           px[s][c] = fmaf(tau, gx, px[s][c]) * rs;
           py[s][c] = py[s][c] * rs;
@@ -315,7 +337,7 @@ __device__ __forceinline__ void tv_tile_impl(const TvLaunch& a, const int k, con
 
 // One tile of one slice.  Tiles whose columns lie strictly inside [0, W-1) need no
 // x-gradient mask and take the unmasked code path.
-template <int CX, int S, int NW, bool TAPE = false>
+template <int CX, int S, int NW, bool TAPE = false, bool COLD = false>
 __device__ __forceinline__ void tv_tile(const TvLaunch& a, const int tile, const int slice,
                                         TvExchange<CX, NW>& xch, TvStage<CX, S, NW>& fst) {
   const int k = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -325,9 +347,9 @@ __device__ __forceinline__ void tv_tile(const TvLaunch& a, const int tile, const
   const int ox = tx * a.IX - a.halo, oy = ty * a.IY - a.halo;
   const bool inner_cols = ox >= 0 && ox + 64 * CX <= a.W - 1;
   if (inner_cols)
-    tv_tile_impl<CX, S, NW, false, TAPE>(a, k, L, ox, oy, base, xch, fst);
+    tv_tile_impl<CX, S, NW, false, TAPE, COLD>(a, k, L, ox, oy, base, xch, fst);
   else
-    tv_tile_impl<CX, S, NW, true, TAPE>(a, k, L, ox, oy, base, xch, fst);
+    tv_tile_impl<CX, S, NW, true, TAPE, COLD>(a, k, L, ox, oy, base, xch, fst);
 }
 
 }  // namespace tvimpl
