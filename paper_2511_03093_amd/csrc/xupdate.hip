@@ -28,6 +28,29 @@ constexpr int kXuMaxThreads = 512;
 
 // `d` is the dual variable, or (d_from_f) the previous f, with d = f - u formed
 // here exactly as the TV epilogue forms it; f_out may then alias `d`.
+// Every slice access is (wave-uniform slice base) + (32-bit lane byte offset):
+// the slice base is formed by scalar arithmetic and the lane offset once, so a
+// load or store costs no vector address arithmetic (plans keep 4 H W < 2^32).
+// The base goes through readfirstlane so that it stays a scalar pair (left to
+// itself the compiler re-associates base + r HW + offset into per-lane 64-bit
+// multiply-adds).
+typedef __attribute__((address_space(1))) char gchar;
+__device__ __forceinline__ gchar* sbase(const void* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (gchar*)(((uint64_t)hi << 32) | lo);
+}
+template <typename T>
+__device__ __forceinline__ T ld_at(const T* base, uint32_t off) {
+  typedef __attribute__((address_space(1))) const T gT;
+  return *(gT*)(sbase(base) + off);
+}
+__device__ __forceinline__ void st_at(float* base, uint32_t off, float v) {
+  typedef __attribute__((address_space(1))) float gT;
+  *(gT*)(sbase(base) + off) = v;
+}
+
 template <int R>
 __global__ __launch_bounds__(kXuMaxThreads) void xupdate_kernel(
     const ZSolve z, const uint32_t* __restrict__ bits, int H, int W, int Wq,
@@ -37,26 +60,34 @@ __global__ __launch_bounds__(kXuMaxThreads) void xupdate_kernel(
   const int h = blockIdx.y * blockDim.y + threadIdx.y;
   if (w >= W || h >= H) return;
   const size_t HW = (size_t)H * W;
-  const size_t p = (size_t)h * W + w;
-  const uint32_t m = load_bits<R>(bits, H, Wq, h, w);
-  const double yv = (double)y[p];
+  const uint32_t off = 4u * (uint32_t)(h * W + w);
+  const uint32_t boff = 4u * (uint32_t)(h * Wq + (w >> 5));
+  const uint32_t bit = (uint32_t)w & 31u;
+  uint32_t m = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t word = ld_at(bits + (size_t)r * H * Wq, boff);
+    m |= ((word >> bit) & 1u) << r;
+  }
+  const double yv = (double)ld_at(y, off);
   double a[R];
   float dv[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const float ur = u[r * HW + p];
-    dv[r] = d_from_f ? d[r * HW + p] - ur : d[r * HW + p];
+    const float ur = ld_at(u + r * HW, off);
+    const float dr = ld_at(d + r * HW, off);
+    dv[r] = d_from_f ? dr - ur : dr;
     a[r] = z.rho * ((double)ur - (double)dv[r]);
     if ((m >> r) & 1u) a[r] += yv;
   }
   pixel_solve<R>(z, m, a);
   if (x_out) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) x_out[r * HW + p] = (float)a[r];
+    for (int r = 0; r < R; ++r) st_at(x_out + r * HW, off, (float)a[r]);
   }
   if (f_out) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) f_out[r * HW + p] = (float)(a[r] + (double)dv[r]);
+    for (int r = 0; r < R; ++r) st_at(f_out + r * HW, off, (float)(a[r] + (double)dv[r]));
   }
 }
 
