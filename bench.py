@@ -37,7 +37,7 @@ TV_TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "tv_traffic_512x512x16.json")
 TV_SOURCES = [os.path.join(ROOT, "paper_2511_03093_amd", "csrc", n) for n in ("tv_impl.hpp", "tv.hip")]
 
 
-EXTRAS = ("batched", "differentiable", "bm3d", "paper_schedule", "paper_volume")
+EXTRAS = ("batched", "differentiable", "bm3d", "paper_schedule", "paper_volume", "kernel_sizes")
 
 
 def parse():
@@ -153,6 +153,67 @@ def timed(fn, steps, warmup):
     e.record()
     e.synchronize()
     return s.elapsed_time(e) / 1e3 / steps
+
+
+def kernel_sizes(reps):
+    """Per-kernel rates at volumes past the bench workload's, beside plain device copies of equal bytes.
+
+    At 512 x 512 x 16 a launch moves 17-52 MB and its ramp-up and drain are a large share of a
+    5-12 us kernel; at 1024^2 x 16 (the BM3D workload's volume) and 2048^2 x 16 (256 MiB per volume,
+    past the 256 MB Infinity Cache) the streaming kernels run at their steady rate.  Inputs are seeded
+    uniform values with Bernoulli(0.5) masks; a kernel's duration does not depend on the values.
+    """
+    import numpy as np
+    import torch
+
+    from paper_2511_03093_amd import cspnp
+
+    out = {}
+    for (H, W, R) in ((1024, 1024, 16), (2048, 2048, 16)):
+        rng = np.random.default_rng([20251103, 99, H])
+        plan = cspnp.Plan((rng.random((R, H, W)) < 0.5).astype(np.uint8), zbc="periodic", denoiser="tv")
+        prm = cspnp.make_params(lam=0.05, rho=1.0, gamma=0.1, iters=1, tv_inner=10)
+        tuned = plan.autotune(prm)
+        g = torch.Generator(device="cuda")
+        g.manual_seed(H)
+        y = torch.rand((H, W), device="cuda", generator=g)
+        u = torch.rand((R, H, W), device="cuda", generator=g)
+        d = torch.rand((R, H, W), device="cuda", generator=g)
+        x = torch.rand((R, H, W), device="cuda", generator=g)
+        f = torch.empty_like(u)
+        o = torch.empty_like(u)
+        h = plan._handle
+        t_xu, _ = time_launches(lambda: cspnp.cspnp_xupdate(h, prm, y.data_ptr(), u.data_ptr(), d.data_ptr(), None,
+                                                            f.data_ptr(), cspnp._stream()), reps)
+        t_tv, _ = time_launches(lambda: cspnp.cspnp_denoise(h, prm, f.data_ptr(), o.data_ptr(), None, None,
+                                                            cspnp._stream()), reps)
+        t_fw, _ = time_launches(lambda: cspnp.cspnp_forward(h, x.data_ptr(), y.data_ptr(), cspnp._stream()), reps)
+        t_ad, _ = time_launches(lambda: cspnp.cspnp_adjoint(h, y.data_ptr(), o.data_ptr(), cspnp._stream()), reps)
+        nv = R * H * W
+        bits = R * H * ((W + 31) // 32) * 4
+        b_op = nv * 4 + H * W * 4 + bits
+        b_xu = nv * 12 + H * W * 4 + bits
+
+        def rate(b, t):
+            return {"us": t * 1e6, "GB/s": b / t / 1e9, "hbm_frac": b / t / 1e9 / HBM_PEAK_GBS}
+
+        def copy_rate(b):
+            n = b // 8
+            src = torch.ones(n, device="cuda")
+            dst = torch.empty(n, device="cuda")
+            t, _ = time_launches(lambda: dst.copy_(src), reps)
+            return {"bytes": 2 * n * 4, "us": t * 1e6, "GB/s": 2 * n * 4 / t / 1e9}
+
+        tv_flops = nv * (TV_FLOPS_PER_PIXEL_ITER * 10 + TV_FLOPS_PER_PIXEL_CALL)
+        out[f"{H}x{W}x{R}"] = {
+            "forward": rate(b_op, t_fw), "adjoint": rate(b_op, t_ad), "xupdate": rate(b_xu, t_xu),
+            "tv_prox": {"us": t_tv * 1e6, "TFLOP/s": tv_flops / t_tv / 1e12,
+                        "valu_frac": tv_flops / t_tv / 1e12 / VALU_PEAK_TFLOPS},
+            "copy_same_bytes_as_operator": copy_rate(b_op), "copy_same_bytes_as_xupdate": copy_rate(b_xu),
+            "tuning": {"tv_tile": list(cspnp.cspnp_tv_shape_info(tuned[0])), "xu_block": tuned[1]}}
+        del plan, y, u, d, x, f, o
+        torch.cuda.empty_cache()
+    return out
 
 
 def batched_vs_plain(steps):
@@ -517,7 +578,7 @@ def main():
     if not a.no_extras:
         runs = {"batched": lambda: batched_vs_plain(a.extra_steps), "differentiable": lambda: fwd_bwd(a.extra_steps),
                 "bm3d": lambda: bm3d_workload(2), "paper_schedule": lambda: paper_schedule(a.extra_steps),
-                "paper_volume": lambda: paper_volume(a.extra_steps)}
+                "paper_volume": lambda: paper_volume(a.extra_steps), "kernel_sizes": lambda: kernel_sizes(a.kernel_reps)}
         for name in EXTRAS:
             if name in extras:
                 t_x = time.perf_counter()

@@ -351,27 +351,49 @@ __global__ __launch_bounds__(kThreads) void xupdate_bwd(const ZSolve z, int peri
                                                         float* __restrict__ ybar, float* __restrict__ ubar,
                                                         float* __restrict__ dbar, double* __restrict__ part_rho,
                                                         double* __restrict__ part_gam) {
-  const size_t HW = (size_t)H * W;
+  using xuimpl::ld_at;
+  using xuimpl::st_at;
+  // slice accesses as scalar base + 32-bit lane offset (H W <= 2^30)
+  const uint32_t HW = (uint32_t)H * (uint32_t)W;
+  const size_t HWs = HW;
   double ar = 0.0, ag = 0.0;
-  for (size_t p = blockIdx.x * (size_t)kThreads + threadIdx.x; p < HW; p += (size_t)gridDim.x * kThreads) {
-    const int h = (int)(p / W), w = (int)(p % W);
+  for (uint32_t p = blockIdx.x * kThreads + threadIdx.x; p < HW; p += gridDim.x * kThreads) {
+    // slice bases are formed afresh in every pass (the empty asm hides the
+    // pointers' identity): hoisted out of the loop, 7 R of them would not fit
+    // the scalar registers
+    const uint32_t* bits_ = bits;
+    const float *fbar_ = fbar, *xbar_ = xbar, *uk_ = uk, *dk_ = dk, *fk_ = fk;
+    float *ubar_ = ubar, *dbar_ = dbar;
+    asm volatile("" : "+s"(bits_), "+s"(fbar_), "+s"(xbar_), "+s"(uk_), "+s"(dk_), "+s"(fk_), "+s"(ubar_), "+s"(dbar_));
+    const uint32_t h = p / (uint32_t)W, w = p - h * (uint32_t)W;
+    const uint32_t off = 4u * p, boff = 4u * (h * (uint32_t)Wq + (w >> 5)), bit = w & 31u;
     uint32_t m = 0;
 #pragma unroll
-    for (int r = 0; r < R; ++r) m |= ((bits[((size_t)r * H + h) * Wq + (w >> 5)] >> (w & 31)) & 1u) << r;
-    double lam[R], xv[R];
+    for (int r = 0; r < R; ++r) m |= ((ld_at(bits_ + (size_t)r * H * Wq, boff) >> bit) & 1u) << r;
+    double lam[R];
     float fb[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      fb[r] = fbar[r * HW + p];
-      lam[r] = (double)fb[r] + (xbar ? (double)xbar[r * HW + p] : 0.0);
-      xv[r] = (double)fk[r * HW + p] - (double)dk[r * HW + p];
+      fb[r] = ld_at(fbar_ + r * HWs, off);
+      lam[r] = (double)fb[r] + (xbar_ ? (double)ld_at(xbar_ + r * HWs, off) : 0.0);
     }
     xuimpl::pixel_solve<R>(z, m, lam);
+    // The state loads go after the solve (not hoisted above it): with both groups
+    // live at once the kernel needed ~450 registers, one wave per SIMD.
+    asm volatile("" ::: "memory");
+    float uv[R], dv[R], fv[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      uv[r] = ld_at(uk_ + r * HWs, off);
+      dv[r] = ld_at(dk_ + r * HWs, off);
+      fv[r] = ld_at(fk_ + r * HWs, off);
+    }
+    auto xv = [&](int r) { return (double)fv[r] - (double)dv[r]; };  // x^{k+1} = f - d
     double yb = 0.0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       if ((m >> r) & 1u) yb += lam[r];
-      const double g = (double)uk[r * HW + p] - (double)dk[r * HW + p] - xv[r];
+      const double g = (double)uv[r] - (double)dv[r] - xv(r);
       ar += lam[r] * g;
       // (L x)_r: chain neighbours, plus the wrap pair when periodic
       double lx;
@@ -379,15 +401,16 @@ __global__ __launch_bounds__(kThreads) void xupdate_bwd(const ZSolve z, int peri
         lx = 0.0;
       } else if (periodic_lap) {
         const int rm = (r + R - 1) % R, rp = (r + 1) % R;
-        lx = 2.0 * xv[r] - xv[rm] - xv[rp];
+        lx = 2.0 * xv(r) - xv(rm) - xv(rp);
       } else {
-        lx = (r > 0 ? xv[r] - xv[r - 1] : 0.0) + (r < R - 1 ? xv[r] - xv[r + 1] : 0.0);
+        lx = (r > 0 ? xv(r) - xv(r - 1) : 0.0) + (r < R - 1 ? xv(r) - xv(r + 1) : 0.0);
       }
       ag -= lam[r] * lx;
-      ubar[r * HW + p] = (float)(z.rho * lam[r]);
-      dbar[r * HW + p] = (float)((double)fb[r] - z.rho * lam[r]);
+      st_at(ubar_ + r * HWs, off, (float)(z.rho * lam[r]));
+      st_at(dbar_ + r * HWs, off, (float)((double)fb[r] - z.rho * lam[r]));
     }
-    ybar[p] += (float)yb;
+    float* yo = ybar;
+    st_at(yo, off, ld_at((const float*)yo, off) + (float)yb);
   }
   double s = block_sum(ar);
   if (threadIdx.x == 0) part_rho[blockIdx.x] = s;

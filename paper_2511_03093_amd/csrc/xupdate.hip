@@ -19,7 +19,9 @@ namespace cspnp {
 namespace {
 
 using xuimpl::load_bits;
+using xuimpl::ld_at;
 using xuimpl::pixel_solve;
+using xuimpl::st_at;
 
 // block shapes (threads along W, rows) selectable per plan
 constexpr int kXuShapes[][2] = {{64, 4}, {64, 8}, {128, 2}, {256, 1}, {64, 2}, {64, 1}};
@@ -28,29 +30,6 @@ constexpr int kXuMaxThreads = 512;
 
 // `d` is the dual variable, or (d_from_f) the previous f, with d = f - u formed
 // here exactly as the TV epilogue forms it; f_out may then alias `d`.
-// Every slice access is (wave-uniform slice base) + (32-bit lane byte offset):
-// the slice base is formed by scalar arithmetic and the lane offset once, so a
-// load or store costs no vector address arithmetic (plans keep 4 H W < 2^32).
-// The base goes through readfirstlane so that it stays a scalar pair (left to
-// itself the compiler re-associates base + r HW + offset into per-lane 64-bit
-// multiply-adds).
-typedef __attribute__((address_space(1))) char gchar;
-__device__ __forceinline__ gchar* sbase(const void* p) {
-  const uint64_t v = reinterpret_cast<uint64_t>(p);
-  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-  return (gchar*)(((uint64_t)hi << 32) | lo);
-}
-template <typename T>
-__device__ __forceinline__ T ld_at(const T* base, uint32_t off) {
-  typedef __attribute__((address_space(1))) const T gT;
-  return *(gT*)(sbase(base) + off);
-}
-__device__ __forceinline__ void st_at(float* base, uint32_t off, float v) {
-  typedef __attribute__((address_space(1))) float gT;
-  *(gT*)(sbase(base) + off) = v;
-}
-
 template <int R>
 __global__ __launch_bounds__(kXuMaxThreads) void xupdate_kernel(
     const ZSolve z, const uint32_t* __restrict__ bits, int H, int W, int Wq,

@@ -53,6 +53,30 @@ __device__ __forceinline__ void pixel_solve(const ZSolve& z, uint32_t m, double 
   }
 }
 
+// Every slice access is (wave-uniform slice base) + (32-bit lane byte offset):
+// the slice base is formed by scalar arithmetic and the lane offset once, so a
+// load or store costs no vector address arithmetic (plans keep H W <= 2^30, so
+// every byte offset within a slice fits 32 bits).
+// The base goes through readfirstlane so that it stays a scalar pair (left to
+// itself the compiler re-associates base + r HW + offset into per-lane 64-bit
+// multiply-adds).
+typedef __attribute__((address_space(1))) char gchar;
+__device__ __forceinline__ gchar* sbase(const void* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (gchar*)(((uint64_t)hi << 32) | lo);
+}
+template <typename T>
+__device__ __forceinline__ T ld_at(const T* base, uint32_t off) {
+  typedef __attribute__((address_space(1))) const T gT;
+  return *(gT*)(sbase(base) + off);
+}
+__device__ __forceinline__ void st_at(float* base, uint32_t off, float v) {
+  typedef __attribute__((address_space(1))) float gT;
+  *(gT*)(sbase(base) + off) = v;
+}
+
 template <int R, typename Word = const uint32_t>
 __device__ __forceinline__ uint32_t load_bits(Word* __restrict__ bits, int H, int Wq, int h, int w) {
   uint32_t m = 0;
