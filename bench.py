@@ -192,7 +192,7 @@ def kernel_sizes(reps):
         nv = R * H * W
         bits = R * H * ((W + 31) // 32) * 4
         b_op = nv * 4 + H * W * 4 + bits
-        b_xu = nv * 12 + H * W * 4 + bits
+        b_xu = nv * 12 + H * W * 4 + H * W * (2 if R <= 16 else 4)
 
         def rate(b, t):
             return {"us": t * 1e6, "GB/s": b / t / 1e9, "hbm_frac": b / t / 1e9 / HBM_PEAK_GBS}
@@ -524,9 +524,10 @@ def main():
     y.copy_(torch.from_numpy(prob.y))
     torch.cuda.synchronize()
 
-    bits_bytes = R * H * ((W + 31) // 32) * 4
+    bits_bytes = R * H * ((W + 31) // 32) * 4              # the operator's bit-planes
+    pmask_bytes = H * W * (2 if R <= 16 else 4)             # the x-step's pixel-major mask words
     b_op = nvox * 4 + H * W * 4 + bits_bytes               # read x / write x, y once, bits once
-    b_xu = nvox * 12 + H * W * 4 + bits_bytes               # read u, d, write f; y, bits
+    b_xu = nvox * 12 + H * W * 4 + pmask_bytes              # read u, d, write f; y, mask words
     b_tv = nvox * 8                                          # read f, write u
     tv_flops = nvox * (TV_FLOPS_PER_PIXEL_ITER * pd["tv_inner"] + TV_FLOPS_PER_PIXEL_CALL)
     kernels = {

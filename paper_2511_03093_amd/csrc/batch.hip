@@ -15,6 +15,8 @@
 #include <memory>
 #include <vector>
 
+#include <type_traits>
+
 #include "tv_impl.hpp"
 #include "xupdate_impl.hpp"
 
@@ -28,23 +30,21 @@ constexpr int kNumXcd = 8;
 
 struct XuProblem {
   ZSolve z;
-  const uint32_t* bits;
+  const void* pmask;  // the plan's pixel-major mask words (uint16 for R <= 16, else uint32)
   const float* y;
   const float* u;
   const float* d;
   float* x;
   float* f;
-  int H, W, Wq, pad;
+  int H, W;
 };
 
 // Pointers read from a problem record are generic; these are device (global)
 // memory, and saying so turns flat accesses into global ones.
 typedef __attribute__((address_space(1))) const float gfloat;
 typedef __attribute__((address_space(1))) float gfloat_w;
-typedef __attribute__((address_space(1))) const uint32_t gword;
 __device__ __forceinline__ const gfloat* to_global(const float* p) { return (const gfloat*)p; }
 __device__ __forceinline__ gfloat_w* to_global(float* p) { return (gfloat_w*)p; }
-__device__ __forceinline__ const gword* to_global(const uint32_t* p) { return (const gword*)p; }
 
 __device__ __forceinline__ bool next_entry(int& e, int& step, int n, bool first) {
   // XCD-aware static schedule over entries [0, n)
@@ -75,7 +75,8 @@ __global__ __launch_bounds__(kXuThreads) void batch_xupdate(const XuProblem* __r
     const int p = en.y * kXuThreads + threadIdx.x;
     if (p >= HW) continue;
     const int h = p / P.W, w = p - h * P.W;
-    const uint32_t m = xuimpl::load_bits<R, const gword>(to_global(P.bits), P.H, P.Wq, h, w);
+    typedef typename std::conditional<(R <= 16), uint16_t, uint32_t>::type MW;
+    const uint32_t m = ((__attribute__((address_space(1))) const MW*)P.pmask)[p];
     const double yv = (double)to_global(P.y)[p];
     const gfloat* __restrict__ us = to_global(P.u);
     const gfloat* __restrict__ ds = to_global(d_from_f ? P.f : P.d);
@@ -97,7 +98,12 @@ __global__ __launch_bounds__(kXuThreads) void batch_xupdate(const XuProblem* __r
     }
     gfloat_w* fo = to_global(P.f);
 #pragma unroll
-    for (int r = 0; r < R; ++r) fo[(size_t)r * HW + p] = (float)(a[r] + (double)dv[r]);
+    for (int r = 0; r < R; ++r) {
+      // converted here, not kept as FP64 across the solve
+      float dr = dv[r];
+      asm volatile("" : "+v"(dr));
+      fo[(size_t)r * HW + p] = (float)(a[r] + (double)dr);
+    }
   }
 }
 
@@ -246,7 +252,7 @@ int prepare(cspnp_batch& b, const cspnp_params* params, const float* const* y, f
     off += align_up(vol * sizeof(float));
     XuProblem& X = b.h_xu[i];
     X.z = make_zsolve(de.R, de.zbc, params[i].rho, params[i].gamma);
-    X.bits = pl.bits;
+    X.pmask = pl.pmask;
     X.y = y[i];
     X.u = u[i];
     X.d = d[i];
@@ -254,7 +260,6 @@ int prepare(cspnp_batch& b, const cspnp_params* params, const float* const* y, f
     X.f = f;
     X.H = de.H;
     X.W = de.W;
-    X.Wq = pl.Wq;
     const int ri = (int)(std::find(b.rvals.begin(), b.rvals.end(), de.R) - b.rvals.begin());
     const int nblk = (de.H * de.W + kXuThreads - 1) / kXuThreads;
     for (int k = 0; k < nblk; ++k) b.h_xu_entries[ri].push_back(int2{i, k});

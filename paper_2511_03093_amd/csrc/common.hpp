@@ -115,6 +115,9 @@ struct cspnp_plan {
   int device = 0;
   int Wq = 0;                    // 32-bit words per bit-plane row
   uint32_t* bits = nullptr;      // device uint32[R][H][Wq]
+  // N = 1: the same masks pixel-major, bit r of pixel p = mask r at p; uint16[H][W]
+  // when R <= 16, uint32[H][W] otherwise (one load per pixel in the x-step)
+  void* pmask = nullptr;
   hipStream_t capture_stream = nullptr;
   cspnp::GraphCache graph;
   int tv_shape = 0;  // index into the TV tile-shape table

@@ -130,6 +130,7 @@ cspnp_plan::~cspnp_plan() {
   graph.clear();
   if (capture_stream) (void)hipStreamDestroy(capture_stream);
   if (bits) (void)hipFree(bits);
+  if (pmask) (void)hipFree(pmask);
   if (dct) (void)hipFree(dct);
   if (ms_scratch) (void)hipFree(ms_scratch);
 }
@@ -197,6 +198,23 @@ CSPNP_API int cspnp_plan_create(const cspnp_desc* desc, const uint8_t* masks, in
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   CSPNP_HIP(hipMemcpyAsync(plan->bits, packed.data(), packed.size() * sizeof(uint32_t),
                            hipMemcpyHostToDevice, st));
+  std::vector<uint16_t> pm16;
+  std::vector<uint32_t> pm32;
+  if (desc->N == 1) {
+    const size_t HW = (size_t)H * W;
+    if (R <= 16) pm16.assign(HW, 0); else pm32.assign(HW, 0u);
+    for (int r = 0; r < R; ++r) {
+      const uint8_t* mr = m + (size_t)r * HW;
+      for (size_t i = 0; i < HW; ++i) {
+        if (R <= 16) pm16[i] |= (uint16_t)(mr[i] << r);
+        else pm32[i] |= uint32_t(mr[i]) << r;
+      }
+    }
+    const size_t nb = R <= 16 ? HW * sizeof(uint16_t) : HW * sizeof(uint32_t);
+    CSPNP_HIP(hipMalloc(&plan->pmask, nb));
+    CSPNP_HIP(hipMemcpyAsync(plan->pmask, R <= 16 ? (const void*)pm16.data() : (const void*)pm32.data(), nb,
+                             hipMemcpyHostToDevice, st));
+  }
   if (desc->N > 1) CSPNP_HIP(hipMalloc(&plan->ms_scratch, multishot_scratch_bytes(*desc)));
   if (desc->denoiser == CSPNP_DENOISER_BM3D) {
     double c[64];

@@ -12,6 +12,8 @@
 // exactly the paper's element-wise update (end of Sec. III-B).
 // One thread per pixel, the z-vector in FP64 registers, FP32 in/out; the
 // kernel streams u, d (8 B/voxel) and writes f = x + d (4 B/voxel): HBM-bound.
+#include <type_traits>
+
 #include "xupdate_impl.hpp"
 
 namespace cspnp {
@@ -30,24 +32,22 @@ constexpr int kXuMaxThreads = 512;
 
 // `d` is the dual variable, or (d_from_f) the previous f, with d = f - u formed
 // here exactly as the TV epilogue forms it; f_out may then alias `d`.
+// The pixel's mask bits are one pixel-major word (uint16 for R <= 16).
+template <int R>
+using MaskWord = typename std::conditional<(R <= 16), uint16_t, uint32_t>::type;
+
 template <int R>
 __global__ __launch_bounds__(kXuMaxThreads) void xupdate_kernel(
-    const ZSolve z, const uint32_t* __restrict__ bits, int H, int W, int Wq,
+    const ZSolve z, const MaskWord<R>* __restrict__ pmask, int H, int W,
     const float* __restrict__ y, const float* __restrict__ u, const float* d, int d_from_f,
     float* __restrict__ x_out, float* f_out) {
   const int w = blockIdx.x * blockDim.x + threadIdx.x;
   const int h = blockIdx.y * blockDim.y + threadIdx.y;
   if (w >= W || h >= H) return;
   const size_t HW = (size_t)H * W;
-  const uint32_t off = 4u * (uint32_t)(h * W + w);
-  const uint32_t boff = 4u * (uint32_t)(h * Wq + (w >> 5));
-  const uint32_t bit = (uint32_t)w & 31u;
-  uint32_t m = 0;
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const uint32_t word = ld_at(bits + (size_t)r * H * Wq, boff);
-    m |= ((word >> bit) & 1u) << r;
-  }
+  const uint32_t pix = (uint32_t)(h * W + w);
+  const uint32_t off = 4u * pix;
+  const uint32_t m = ld_at(pmask, (uint32_t)sizeof(MaskWord<R>) * pix);
   const double yv = (double)ld_at(y, off);
   double a[R];
   float dv[R];
@@ -66,7 +66,12 @@ __global__ __launch_bounds__(kXuMaxThreads) void xupdate_kernel(
   }
   if (f_out) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) st_at(f_out + r * HW, off, (float)(a[r] + (double)dv[r]));
+    for (int r = 0; r < R; ++r) {
+      // converted here, not kept as FP64 across the solve
+      float dr = dv[r];
+      asm volatile("" : "+v"(dr));
+      st_at(f_out + r * HW, off, (float)(a[r] + (double)dr));
+    }
   }
 }
 
@@ -122,8 +127,8 @@ hipError_t launch_r(const cspnp_plan& pl, const ZSolve& zs, const float* y, cons
   const int bx = kXuShapes[pl.xu_block][0], by = kXuShapes[pl.xu_block][1];
   dim3 block(bx, by);
   dim3 grid((de.W + bx - 1) / bx, (de.H + by - 1) / by);
-  hipLaunchKernelGGL(xupdate_kernel<R>, grid, block, 0, s, zs, pl.bits, de.H, de.W, pl.Wq, y, u, d,
-                     d_from_f, x_out, f_out);
+  hipLaunchKernelGGL(xupdate_kernel<R>, grid, block, 0, s, zs, static_cast<const MaskWord<R>*>(pl.pmask), de.H,
+                     de.W, y, u, d, d_from_f, x_out, f_out);
   return hipGetLastError();
 }
 
