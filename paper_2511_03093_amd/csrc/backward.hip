@@ -85,7 +85,7 @@ struct TvbArgs {
   float theta, inv_theta, tau;
 };
 
-constexpr int kTvbCX = 2, kTvbS = 8, kTvbNW = 16;
+constexpr int kTvbCX = 2, kTvbS = 7, kTvbNW = 16;
 
 template <int CX, int S, int NW>
 __global__ __launch_bounds__(64 * NW) void tvb_tile(const TvbArgs a) {

@@ -38,8 +38,8 @@ __global__ __launch_bounds__(64 * NW) void tv_kernel(const TvLaunch a) {
   tv_tile<CX, S, NW, false, COLD>(a, blockIdx.x, blockIdx.y, xch, fst);
 }
 
-// The backward's tape: the same tile with p^1..p^K written out (128 x 128 tiles).
-constexpr int kTapeCX = 2, kTapeS = 8, kTapeNW = 16;
+// The backward's tape: the same tile with p^1..p^K written out (128 x 192 tiles).
+constexpr int kTapeCX = 2, kTapeS = 12, kTapeNW = 16;
 
 __global__ __launch_bounds__(64 * kTapeNW) void tv_tape_kernel(const TvLaunch a) {
   __shared__ tvimpl::TvExchange<kTapeCX, kTapeNW> xch;
