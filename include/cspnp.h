@@ -235,7 +235,11 @@ int cspnp_solve_ckpt(const cspnp_plan* plan, const cspnp_params* params, const f
  * cspnp_solve_ckpt with the same params and y) and accumulates
  *   y_bar (float[N][H][W], overwritten)  and
  *   param_bar (device double[3], overwritten) = d<x_bar,x^K>/d(rho, lambda, gamma).
- * x_bar: volume (read).  Deterministic (fixed-order FP64 reductions). */
+ * x_bar: volume (read).  Deterministic (fixed-order FP64 reductions).
+ * Captured into a HIP graph on the first call for a given (params,
+ * ckpt_every, pointers) and replayed by later identical calls (the plan's
+ * graph cache, shared with cspnp_solve); CSPNP_FLAG_NO_GRAPH launches
+ * directly. */
 int cspnp_solve_bwd(const cspnp_plan* plan, const cspnp_params* params, const float* y, int ckpt_every,
                     const float* ckpt, const float* x_bar, float* y_bar, double* param_bar, void* ws,
                     void* stream);

@@ -762,6 +762,39 @@ CSPNP_API int cspnp_solve_bwd(const cspnp_plan* cplan, const cspnp_params* param
     return fail(CSPNP_EINVAL, "param_bar must be an 8-byte aligned device pointer");
   if (ws == nullptr || reinterpret_cast<uintptr_t>(ws) % 256) return fail(CSPNP_EINVAL, "ws must be 256-byte aligned");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  CSPNP_HIP(enqueue_backward(*cplan, *params, y, ckpt_every, ckpt, x_bar, y_bar, param_bar, static_cast<char*>(ws), st));
+  char* wsc = static_cast<char*>(ws);
+  if (params->flags & CSPNP_FLAG_NO_GRAPH) {
+    CSPNP_HIP(enqueue_backward(*cplan, *params, y, ckpt_every, ckpt, x_bar, y_bar, param_bar, wsc, st));
+    return CSPNP_OK;
+  }
+  // captured once per (parameters, pointers) into the plan's graph cache, like cspnp_solve
+  cspnp_plan* plan = const_cast<cspnp_plan*>(cplan);
+  std::vector<uint8_t> key;
+  const char tag[4] = {'b', 'w', 'd', 0};
+  key_append(key, tag);
+  key_append(key, params->lambda); key_append(key, params->rho); key_append(key, params->gamma);
+  key_append(key, params->iters); key_append(key, params->tv_inner); key_append(key, params->tv_tau);
+  key_append(key, ckpt_every);
+  key_append(key, y); key_append(key, ckpt); key_append(key, x_bar); key_append(key, y_bar);
+  key_append(key, param_bar); key_append(key, ws);
+  GraphEntry* ge = plan->graph.find(key);
+  if (!ge) {
+    CSPNP_HIP(hipStreamBeginCapture(plan->capture_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = enqueue_backward(*plan, *params, y, ckpt_every, ckpt, x_bar, y_bar, param_bar, wsc,
+                                    plan->capture_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(plan->capture_stream, &g);
+    if (e != hipSuccess) { if (g) (void)hipGraphDestroy(g); return hip_fail(e, "backward launch during capture"); }
+    if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+    hipGraphExec_t ex = nullptr;
+    hipError_t e3 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (e3 != hipSuccess) { (void)hipGraphDestroy(g); return hip_fail(e3, "hipGraphInstantiate"); }
+    ge = &plan->graph.slot();
+    ge->graph = g;
+    ge->exec = ex;
+    ge->key = key;
+    ge->last_use = ++plan->graph.clock;
+  }
+  CSPNP_HIP(hipGraphLaunch(ge->exec, st));
   return CSPNP_OK;
 }

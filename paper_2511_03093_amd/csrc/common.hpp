@@ -61,6 +61,13 @@ struct TvShapeInfo {
   int cols, rows; // tile size in pixels
 };
 
+// Appends the bytes of v to a graph-cache key.
+template <typename T>
+inline void key_append(std::vector<uint8_t>& k, const T& v) {
+  const uint8_t* p = reinterpret_cast<const uint8_t*>(&v);
+  k.insert(k.end(), p, p + sizeof(T));
+}
+
 // Captured iteration graphs of a plan, keyed by (parameters, pointers); a few
 // are kept (least recently used evicted) so alternating call patterns replay.
 struct GraphEntry {

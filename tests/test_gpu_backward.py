@@ -150,3 +150,18 @@ def test_full_size_gradients_vs_central_differences(cs):
         fd = (float(loss_at(y0 + h * v, *base)) - float(loss_at(y0 - h * v, *base))) / (2 * h)
         an = float(torch.sum(y.grad.double() * v.double()))
         assert rel(an, fd) < 1e-2, (an, fd)
+
+
+def test_bwd_graph_replay_equals_direct_launch(cs):
+    """The captured backward (first call captures, the second replays) equals direct launches bit for bit."""
+    announce("bwd-graph")
+    prob = synth.make_problem(64, 72, 8, 1, n_blobs=6, seed=(47, 1))
+    p = oracle.Params(denoiser="tv", lam=0.05, rho=1.0, gamma=0.1, iters=6, tv_inner=10, zbc="periodic")
+    plan = cs.Plan(prob.masks, zbc="periodic", denoiser="tv")
+    y = to_gpu(prob.y)
+    xbar = to_gpu(np.random.default_rng([48]).normal(size=prob.gt.shape).astype(np.float32))
+    runs = [gpu_vjp(cs, plan, cs.params_from(p), y, xbar, 4) for _ in range(2)]
+    direct = gpu_vjp(cs, plan, cs.params_from(p, flags=cs.FLAG_NO_GRAPH), y, xbar, 4)
+    for r in runs[1:] + [direct]:
+        for a, b in zip(r, runs[0]):
+            np.testing.assert_array_equal(a, b)
