@@ -36,6 +36,10 @@ __device__ __forceinline__ float from_left(float v) {
 __device__ __forceinline__ float from_right(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, true));
 }
+// lane i <- lane i+1; lane 63 keeps `own` (no source lane: the DPP write is disabled)
+__device__ __forceinline__ float from_right_or(float own, float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(own), __float_as_int(v), 0x130, 0xF, 0xF, false));
+}
 
 // Buffer resources over one H x W slice.  Every offset the tile uses is clamped
 // into the slice, so the hardware range check is never what keeps an access in
@@ -67,15 +71,20 @@ using TvExchange = float[2][NW][2][64 * CX];
 template <int CX, int S, int NW>
 using TvStage = float[NW][S * CX][64];
 
-// BX: the tile reaches a column outside [0, W-1), so the x-gradient needs its
-// boundary mask.  Rows without a y-gradient (the last image row, and rows outside
-// the image) are wave-uniform and take a branch of their own.
+// BX: the tile is wider than the image, so columns outside it need the x-gradient
+// mask.  Otherwise every tile lies inside [0, W) (edge tiles are moved inward) and
+// the only column without an x-gradient inside the tile is W-1, the last column
+// of lane 63 in the right edge tile: there the right neighbour taken is the pixel
+// itself, so g_x = w - w = 0 exactly, with no mask.  Rows without a y-gradient (the
+// last image row, and rows outside the image) are wave-uniform and take a branch
+// of their own.  Interior (written) columns are [ix0, ix1).
 // COLD: the launch starts from p = 0 (no p_in).  Every value the first inner
 // iteration exchanges is then +0, so it is published, and the barrier passed,
 // while the tile's loads are still in flight: each wave starts computing as soon
 // as its own rows have arrived.
 template <int CX, int S, int NW, bool BX, bool TAPE = false, bool COLD = false>
 __device__ __forceinline__ void tv_tile_impl(const TvLaunch& a, const int k, const int L, const int ox, const int oy,
+                                             const int ix0, const int ix1,
                                              const size_t base, TvExchange<CX, NW>& xch, TvStage<CX, S, NW>& fst) {
   // No implicit contraction: a p value must round identically whether its
   // neighbour reads it from a register or through the LDS exchange (the
@@ -192,8 +201,8 @@ __device__ __forceinline__ void tv_tile_impl(const TvLaunch& a, const int k, con
     return __builtin_amdgcn_readfirstlane(m);
   };
   auto col_out = [&](int c) {
-    const int tcc = L * CX + c;
-    return tcc >= a.halo && tcc < a.halo + a.IX && c0 + c < a.W;
+    const int gc = c0 + c;
+    return gc >= ix0 && gc < ix1;
   };
 
   const float tau = a.tau;
@@ -232,7 +241,8 @@ __device__ __forceinline__ void tv_tile_impl(const TvLaunch& a, const int k, con
       float gxs[CX];
 #pragma unroll
       for (int c = 0; c < CX; ++c) {
-        const float d = ((c < CX - 1) ? wcur[c + 1] : from_right(wcur[0])) - wcur[c];
+        const float d = ((c < CX - 1) ? wcur[c + 1] : (BX ? from_right(wcur[0]) : from_right_or(wcur[c], wcur[0]))) -
+                        wcur[c];
         gxs[c] = BX ? d * colx[c] : d;
       }
       if ((rows_gy >> s) & 1u) {
@@ -335,8 +345,8 @@ __device__ __forceinline__ void tv_tile_impl(const TvLaunch& a, const int k, con
   }
 }
 
-// One tile of one slice.  Tiles whose columns lie strictly inside [0, W-1) need no
-// x-gradient mask and take the unmasked code path.
+// One tile of one slice.  When the image is at least a tile wide every tile lies
+// inside it and takes the unmasked code path; otherwise the masked one.
 template <int CX, int S, int NW, bool TAPE = false, bool COLD = false>
 __device__ __forceinline__ void tv_tile(const TvLaunch& a, const int tile, const int slice,
                                         TvExchange<CX, NW>& xch, TvStage<CX, S, NW>& fst) {
@@ -344,12 +354,16 @@ __device__ __forceinline__ void tv_tile(const TvLaunch& a, const int tile, const
   const int L = threadIdx.x & 63;
   const int tx = tile % a.tilesX, ty = tile / a.tilesX;
   const size_t base = (size_t)slice * a.H * a.W;
-  const int ox = tx * a.IX - a.halo, oy = ty * a.IY - a.halo;
-  const bool inner_cols = ox >= 0 && ox + 64 * CX <= a.W - 1;
-  if (inner_cols)
-    tv_tile_impl<CX, S, NW, false, TAPE, COLD>(a, k, L, ox, oy, base, xch, fst);
-  else
-    tv_tile_impl<CX, S, NW, true, TAPE, COLD>(a, k, L, ox, oy, base, xch, fst);
+  const int ix0 = tx * a.IX, ix1 = min(ix0 + a.IX, a.W);
+  const int oy = ty * a.IY - a.halo;
+  if (a.W >= 64 * CX) {
+    // edge tiles moved inward to the image edge: the interior keeps a halo of
+    // `halo` columns on every side that is not the image boundary
+    const int ox = min(max(ix0 - a.halo, 0), a.W - 64 * CX);
+    tv_tile_impl<CX, S, NW, false, TAPE, COLD>(a, k, L, ox, oy, ix0, ix1, base, xch, fst);
+  } else {
+    tv_tile_impl<CX, S, NW, true, TAPE, COLD>(a, k, L, ix0 - a.halo, oy, ix0, ix1, base, xch, fst);
+  }
 }
 
 }  // namespace tvimpl
