@@ -86,6 +86,64 @@ __global__ __launch_bounds__(kOpThreads) void forward_kernel(const float* __rest
   }
 }
 
+// The same for one shot (N = 1) with the plan's pixel-major mask words (MW =
+// uint16 for R <= 16, else uint32; bit r of a pixel's word is mask r): the VEC
+// words of a thread come in one load instead of one bit-plane word per slice.
+template <typename MW>
+struct MaskVec4;
+template <>
+struct MaskVec4<uint16_t> {
+  using T = ushort4;
+};
+template <>
+struct MaskVec4<uint32_t> {
+  using T = uint4;
+};
+
+template <typename MW>
+__global__ __launch_bounds__(kOpThreads) void forward_pm_kernel(const float* __restrict__ x, float* __restrict__ y,
+                                                                const MW* __restrict__ pmask, int H, int W, int R) {
+  const int w0 = (blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  const int h = blockIdx.y * blockDim.y + threadIdx.y;
+  if (w0 >= W || h >= H) return;
+  const size_t HW = (size_t)H * W;
+  const size_t p = (size_t)h * W + w0;
+  const typename MaskVec4<MW>::T mv = *reinterpret_cast<const typename MaskVec4<MW>::T*>(pmask + p);
+  const uint32_t mw[4] = {mv.x, mv.y, mv.z, mv.w};
+  float acc[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int r0 = 0; r0 < R; r0 += kChunk) {
+    float4 xv[kChunk];
+#pragma unroll
+    for (int q = 0; q < kChunk; ++q) xv[q] = nt_load(xv[q], x + (size_t)min(r0 + q, R - 1) * HW + p);
+#pragma unroll
+    for (int q = 0; q < kChunk; ++q) {
+      if (r0 + q >= R) break;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc[i] += ((mw[i] >> (r0 + q)) & 1u) ? Vec<4>::get(xv[q], i) : 0.f;
+    }
+  }
+  *reinterpret_cast<float4*>(y + p) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+}
+
+template <typename MW>
+__global__ __launch_bounds__(kOpThreads) void adjoint_pm_kernel(const float* __restrict__ y, float* __restrict__ x,
+                                                                const MW* __restrict__ pmask, int H, int W, int R) {
+  const int w0 = (blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  const int h = blockIdx.y * blockDim.y + threadIdx.y;
+  if (w0 >= W || h >= H) return;
+  const size_t HW = (size_t)H * W;
+  const size_t p = (size_t)h * W + w0;
+  const typename MaskVec4<MW>::T mv = *reinterpret_cast<const typename MaskVec4<MW>::T*>(pmask + p);
+  const uint32_t mw[4] = {mv.x, mv.y, mv.z, mv.w};
+  const float4 yv = *reinterpret_cast<const float4*>(y + p);
+  for (int r = 0; r < R; ++r) {
+    float4 out;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) Vec<4>::set(out, i, ((mw[i] >> r) & 1u) ? Vec<4>::get(yv, i) : 0.f);
+    nt_store(out, x + (size_t)r * HW + p);
+  }
+}
+
 // x[j*R + r][p] = bit_r(p) * y[j][p]
 template <int VEC>
 __global__ __launch_bounds__(kOpThreads) void adjoint_kernel(const float* __restrict__ y,
@@ -143,13 +201,33 @@ void op_launch(K kernel, const cspnp_plan& pl, const float* in, float* out, hipS
 }  // namespace
 
 hipError_t launch_forward(const cspnp_plan& pl, const float* x, float* y, hipStream_t s) {
-  if (vec4_ok(pl.desc.W, x, y)) op_launch(forward_kernel<4>, pl, x, y, s, 4);
+  if (pl.desc.N == 1 && vec4_ok(pl.desc.W, x, y)) {
+    const auto& d = pl.desc;
+    const dim3 block = op_block(d.W, 4);
+    const dim3 grid((d.W / 4 + block.x - 1) / block.x, (d.H + block.y - 1) / block.y);
+    if (d.R <= 16)
+      hipLaunchKernelGGL(forward_pm_kernel<uint16_t>, grid, block, 0, s, x, y, static_cast<const uint16_t*>(pl.pmask),
+                         d.H, d.W, d.R);
+    else
+      hipLaunchKernelGGL(forward_pm_kernel<uint32_t>, grid, block, 0, s, x, y, static_cast<const uint32_t*>(pl.pmask),
+                         d.H, d.W, d.R);
+  } else if (vec4_ok(pl.desc.W, x, y)) op_launch(forward_kernel<4>, pl, x, y, s, 4);
   else op_launch(forward_kernel<1>, pl, x, y, s, 1);
   return hipGetLastError();
 }
 
 hipError_t launch_adjoint(const cspnp_plan& pl, const float* y, float* x, hipStream_t s) {
-  if (vec4_ok(pl.desc.W, x, y)) op_launch(adjoint_kernel<4>, pl, y, x, s, 4);
+  if (pl.desc.N == 1 && vec4_ok(pl.desc.W, x, y)) {
+    const auto& d = pl.desc;
+    const dim3 block = op_block(d.W, 4);
+    const dim3 grid((d.W / 4 + block.x - 1) / block.x, (d.H + block.y - 1) / block.y);
+    if (d.R <= 16)
+      hipLaunchKernelGGL(adjoint_pm_kernel<uint16_t>, grid, block, 0, s, y, x, static_cast<const uint16_t*>(pl.pmask),
+                         d.H, d.W, d.R);
+    else
+      hipLaunchKernelGGL(adjoint_pm_kernel<uint32_t>, grid, block, 0, s, y, x, static_cast<const uint32_t*>(pl.pmask),
+                         d.H, d.W, d.R);
+  } else if (vec4_ok(pl.desc.W, x, y)) op_launch(adjoint_kernel<4>, pl, y, x, s, 4);
   else op_launch(adjoint_kernel<1>, pl, y, x, s, 1);
   return hipGetLastError();
 }
