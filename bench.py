@@ -190,9 +190,9 @@ def kernel_sizes(reps):
         t_fw, _ = time_launches(lambda: cspnp.cspnp_forward(h, x.data_ptr(), y.data_ptr(), cspnp._stream()), reps)
         t_ad, _ = time_launches(lambda: cspnp.cspnp_adjoint(h, y.data_ptr(), o.data_ptr(), cspnp._stream()), reps)
         nv = R * H * W
-        bits = R * H * ((W + 31) // 32) * 4
-        b_op = nv * 4 + H * W * 4 + bits
-        b_xu = nv * 12 + H * W * 4 + H * W * (2 if R <= 16 else 4)
+        pm = H * W * (2 if R <= 16 else 4)
+        b_op = nv * 4 + H * W * 4 + pm
+        b_xu = nv * 12 + H * W * 4 + pm
 
         def rate(b, t):
             return {"us": t * 1e6, "GB/s": b / t / 1e9, "hbm_frac": b / t / 1e9 / HBM_PEAK_GBS}
@@ -524,9 +524,8 @@ def main():
     y.copy_(torch.from_numpy(prob.y))
     torch.cuda.synchronize()
 
-    bits_bytes = R * H * ((W + 31) // 32) * 4              # the operator's bit-planes
-    pmask_bytes = H * W * (2 if R <= 16 else 4)             # the x-step's pixel-major mask words
-    b_op = nvox * 4 + H * W * 4 + bits_bytes               # read x / write x, y once, bits once
+    pmask_bytes = H * W * (2 if R <= 16 else 4)             # the pixel-major mask words (one shot)
+    b_op = nvox * 4 + H * W * 4 + pmask_bytes              # read x / write x, y once, mask words once
     b_xu = nvox * 12 + H * W * 4 + pmask_bytes              # read u, d, write f; y, mask words
     b_tv = nvox * 8                                          # read f, write u
     tv_flops = nvox * (TV_FLOPS_PER_PIXEL_ITER * pd["tv_inner"] + TV_FLOPS_PER_PIXEL_CALL)

@@ -1,8 +1,9 @@
 // Forward operator and adjoint of the DMD-coded acquisition (Sec. III-A,
-// eq. (model-slice)), on bit-packed masks.  HBM-bound streaming kernels: each
-// thread owns VEC consecutive pixels of one row; 64-lane waves read 64*VEC
-// consecutive floats per slice, and the VEC mask bits of a slice share one
-// 32-bit word of the bit-plane.
+// eq. (model-slice)), on packed masks.  HBM-bound streaming kernels: each thread
+// owns VEC consecutive pixels of one row; 64-lane waves read 64*VEC consecutive
+// floats per slice.  One shot (N = 1): the masks come as pixel-major words (all R
+// bits of a pixel in one word).  N > 1: bit-planes, where the VEC mask bits of a
+// slice share one 32-bit word.
 #include "common.hpp"
 
 namespace cspnp {
@@ -87,62 +88,91 @@ __global__ __launch_bounds__(kOpThreads) void forward_kernel(const float* __rest
 }
 
 // The same for one shot (N = 1) with the plan's pixel-major mask words (MW =
-// uint16 for R <= 16, else uint32; bit r of a pixel's word is mask r): the VEC
-// words of a thread come in one load instead of one bit-plane word per slice.
-template <typename MW>
-struct MaskVec4;
-template <>
-struct MaskVec4<uint16_t> {
-  using T = ushort4;
+// uint16 for R <= 16, else uint32; bit r of a pixel's word is mask r): a thread's
+// VEC words come in one load instead of one bit-plane word per slice.  Two pixels
+// per thread (2048 waves at 512x512) measured faster than four (1024 waves) and
+// level with one.
+// VEC consecutive mask words of one thread
+template <typename MW, int VEC>
+struct MaskWords {
+  uint32_t w[VEC];
+  __device__ explicit MaskWords(const MW* p) {
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) w[i] = p[i];
+  }
 };
 template <>
-struct MaskVec4<uint32_t> {
-  using T = uint4;
+struct Vec<2> {
+  using T = float2;
+  static __device__ float get(const T& v, int i) { return i == 0 ? v.x : v.y; }
+  static __device__ void set(T& v, int i, float x) {
+    if (i == 0) v.x = x; else v.y = x;
+  }
 };
+__device__ __forceinline__ float2 nt_load(const float2&, const float* p) {
+  typedef float f2n __attribute__((ext_vector_type(2)));
+  const f2n w = __builtin_nontemporal_load(reinterpret_cast<const f2n*>(p));
+  return make_float2(w.x, w.y);
+}
+__device__ __forceinline__ void nt_store(const float2& v, float* p) {
+  typedef float f2n __attribute__((ext_vector_type(2)));
+  const f2n w = {v.x, v.y};
+  __builtin_nontemporal_store(w, reinterpret_cast<f2n*>(p));
+}
 
-template <typename MW>
+template <typename MW, int VEC>
 __global__ __launch_bounds__(kOpThreads) void forward_pm_kernel(const float* __restrict__ x, float* __restrict__ y,
                                                                 const MW* __restrict__ pmask, int H, int W, int R) {
-  const int w0 = (blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  using V = Vec<VEC>;
+  const int w0 = (blockIdx.x * blockDim.x + threadIdx.x) * VEC;
   const int h = blockIdx.y * blockDim.y + threadIdx.y;
   if (w0 >= W || h >= H) return;
   const size_t HW = (size_t)H * W;
   const size_t p = (size_t)h * W + w0;
-  const typename MaskVec4<MW>::T mv = *reinterpret_cast<const typename MaskVec4<MW>::T*>(pmask + p);
-  const uint32_t mw[4] = {mv.x, mv.y, mv.z, mv.w};
-  float acc[4] = {0.f, 0.f, 0.f, 0.f};
+  const MaskWords<MW, VEC> mk(pmask + p);
+  const uint32_t* mw = mk.w;
+  float acc[VEC];
+#pragma unroll
+  for (int i = 0; i < VEC; ++i) acc[i] = 0.f;
   for (int r0 = 0; r0 < R; r0 += kChunk) {
-    float4 xv[kChunk];
+    typename V::T xv[kChunk];
 #pragma unroll
     for (int q = 0; q < kChunk; ++q) xv[q] = nt_load(xv[q], x + (size_t)min(r0 + q, R - 1) * HW + p);
 #pragma unroll
     for (int q = 0; q < kChunk; ++q) {
       if (r0 + q >= R) break;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) acc[i] += ((mw[i] >> (r0 + q)) & 1u) ? Vec<4>::get(xv[q], i) : 0.f;
+      for (int i = 0; i < VEC; ++i) acc[i] += ((mw[i] >> (r0 + q)) & 1u) ? V::get(xv[q], i) : 0.f;
     }
   }
-  *reinterpret_cast<float4*>(y + p) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+  typename V::T out;
+#pragma unroll
+  for (int i = 0; i < VEC; ++i) V::set(out, i, acc[i]);
+  *reinterpret_cast<typename V::T*>(y + p) = out;
 }
 
-template <typename MW>
+template <typename MW, int VEC>
 __global__ __launch_bounds__(kOpThreads) void adjoint_pm_kernel(const float* __restrict__ y, float* __restrict__ x,
                                                                 const MW* __restrict__ pmask, int H, int W, int R) {
-  const int w0 = (blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  using V = Vec<VEC>;
+  const int w0 = (blockIdx.x * blockDim.x + threadIdx.x) * VEC;
   const int h = blockIdx.y * blockDim.y + threadIdx.y;
   if (w0 >= W || h >= H) return;
   const size_t HW = (size_t)H * W;
   const size_t p = (size_t)h * W + w0;
-  const typename MaskVec4<MW>::T mv = *reinterpret_cast<const typename MaskVec4<MW>::T*>(pmask + p);
-  const uint32_t mw[4] = {mv.x, mv.y, mv.z, mv.w};
-  const float4 yv = *reinterpret_cast<const float4*>(y + p);
+  const MaskWords<MW, VEC> mk(pmask + p);
+  const uint32_t* mw = mk.w;
+  const typename V::T yv = *reinterpret_cast<const typename V::T*>(y + p);
   for (int r = 0; r < R; ++r) {
-    float4 out;
+    typename V::T out;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) Vec<4>::set(out, i, ((mw[i] >> r) & 1u) ? Vec<4>::get(yv, i) : 0.f);
+    for (int i = 0; i < VEC; ++i) V::set(out, i, ((mw[i] >> r) & 1u) ? V::get(yv, i) : 0.f);
     nt_store(out, x + (size_t)r * HW + p);
   }
 }
+
+// pixels per thread of the one-shot operator kernels
+constexpr int kPmVec = 2;
 
 // x[j*R + r][p] = bit_r(p) * y[j][p]
 template <int VEC>
@@ -203,13 +233,13 @@ void op_launch(K kernel, const cspnp_plan& pl, const float* in, float* out, hipS
 hipError_t launch_forward(const cspnp_plan& pl, const float* x, float* y, hipStream_t s) {
   if (pl.desc.N == 1 && vec4_ok(pl.desc.W, x, y)) {
     const auto& d = pl.desc;
-    const dim3 block = op_block(d.W, 4);
-    const dim3 grid((d.W / 4 + block.x - 1) / block.x, (d.H + block.y - 1) / block.y);
+    const dim3 block = op_block(d.W, kPmVec);
+    const dim3 grid((d.W / kPmVec + block.x - 1) / block.x, (d.H + block.y - 1) / block.y);
     if (d.R <= 16)
-      hipLaunchKernelGGL(forward_pm_kernel<uint16_t>, grid, block, 0, s, x, y, static_cast<const uint16_t*>(pl.pmask),
+      hipLaunchKernelGGL((forward_pm_kernel<uint16_t, kPmVec>), grid, block, 0, s, x, y, static_cast<const uint16_t*>(pl.pmask),
                          d.H, d.W, d.R);
     else
-      hipLaunchKernelGGL(forward_pm_kernel<uint32_t>, grid, block, 0, s, x, y, static_cast<const uint32_t*>(pl.pmask),
+      hipLaunchKernelGGL((forward_pm_kernel<uint32_t, kPmVec>), grid, block, 0, s, x, y, static_cast<const uint32_t*>(pl.pmask),
                          d.H, d.W, d.R);
   } else if (vec4_ok(pl.desc.W, x, y)) op_launch(forward_kernel<4>, pl, x, y, s, 4);
   else op_launch(forward_kernel<1>, pl, x, y, s, 1);
@@ -219,13 +249,13 @@ hipError_t launch_forward(const cspnp_plan& pl, const float* x, float* y, hipStr
 hipError_t launch_adjoint(const cspnp_plan& pl, const float* y, float* x, hipStream_t s) {
   if (pl.desc.N == 1 && vec4_ok(pl.desc.W, x, y)) {
     const auto& d = pl.desc;
-    const dim3 block = op_block(d.W, 4);
-    const dim3 grid((d.W / 4 + block.x - 1) / block.x, (d.H + block.y - 1) / block.y);
+    const dim3 block = op_block(d.W, kPmVec);
+    const dim3 grid((d.W / kPmVec + block.x - 1) / block.x, (d.H + block.y - 1) / block.y);
     if (d.R <= 16)
-      hipLaunchKernelGGL(adjoint_pm_kernel<uint16_t>, grid, block, 0, s, y, x, static_cast<const uint16_t*>(pl.pmask),
+      hipLaunchKernelGGL((adjoint_pm_kernel<uint16_t, kPmVec>), grid, block, 0, s, y, x, static_cast<const uint16_t*>(pl.pmask),
                          d.H, d.W, d.R);
     else
-      hipLaunchKernelGGL(adjoint_pm_kernel<uint32_t>, grid, block, 0, s, y, x, static_cast<const uint32_t*>(pl.pmask),
+      hipLaunchKernelGGL((adjoint_pm_kernel<uint32_t, kPmVec>), grid, block, 0, s, y, x, static_cast<const uint32_t*>(pl.pmask),
                          d.H, d.W, d.R);
   } else if (vec4_ok(pl.desc.W, x, y)) op_launch(adjoint_kernel<4>, pl, y, x, s, 4);
   else op_launch(adjoint_kernel<1>, pl, y, x, s, 1);
