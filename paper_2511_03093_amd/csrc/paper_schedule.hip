@@ -6,8 +6,9 @@
 //           at strength lambda / (rho + c_n gamma), c_n the number of z-neighbours
 //           (2 with the periodic wrap; the newest available neighbour values);
 //   d-step: d = d + v - u.
-// The sweep is sequential in n, so each slice is its own launch (its TV tiles
-// fill only part of the device; this is the schedule's cost, measured as such).
+// The sweep is sequential in n, so each slice is its own launch, with a tile
+// shape chosen for one slice (small tiles over many CUs); the sequential sweep is
+// the schedule's cost, measured as such.
 #include <algorithm>
 
 #include "common.hpp"
@@ -53,6 +54,29 @@ __global__ __launch_bounds__(256) void dstep(size_t n, float* __restrict__ d, co
 
 unsigned grid_for(size_t n) { return (unsigned)std::min<size_t>((n + 255) / 256, 8192); }
 
+// TV tile shape for a launch over NR slices on `cus` compute units: the fewest
+// tile-pixels one CU works through (tile size x ceil(tiles / CUs)), then the
+// larger block.  For one slice this picks small tiles spread over the device.
+int tv_shape_for_cus(int H, int W, int NR, int tv_inner, int cus) {
+  const int halo = tv_inner;  // single pass (tv_inner <= 16 in this schedule's launches)
+  long best = -1;
+  int bi = 0, bthreads = 0;
+  for (int i = 0; i < tv_num_shapes(); ++i) {
+    const TvShapeInfo s = tv_shape_info(i);
+    const int ix = s.cols - 2 * halo, iy = s.rows - 2 * halo;
+    if (ix < 8 || iy < 8) continue;
+    const long tiles = (long)((W + ix - 1) / ix) * ((H + iy - 1) / iy) * NR;
+    const long cost = (tiles + cus - 1) / cus * (long)s.cols * s.rows;
+    const int threads = 64 * s.nw;
+    if (best < 0 || cost < best || (cost == best && threads > bthreads)) {
+      best = cost;
+      bi = i;
+      bthreads = threads;
+    }
+  }
+  return best < 0 ? tv_default_shape(H, W, NR, tv_inner) : bi;
+}
+
 }  // namespace
 
 size_t paper_workspace_bytes(const cspnp_plan& pl, int tv_inner) {
@@ -70,7 +94,10 @@ hipError_t enqueue_paper_iterations(const cspnp_plan& pl, const cspnp_params& p,
   void* tws = static_cast<char*>(ws) + align_up(HW * sizeof(float));
   const ZSolve zs = make_zsolve(de.R, de.zbc, p.rho, 0.0);  // the paper's v-step carries no temporal term
   const bool periodic = de.zbc == CSPNP_ZBC_PERIODIC;
-  const int shape = tv_default_shape(de.H, de.W, 1, p.tv_inner);
+  // each u-step launch denoises one slice: small tiles spread it over the device
+  int cus = 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, pl.device) != hipSuccess || cus < 1) cus = 256;
+  const int shape = tv_shape_for_cus(de.H, de.W, 1, p.tv_inner, cus);
   for (int k = 0; k < p.iters; ++k) {
     hipError_t e = launch_xupdate(pl, zs, y, u, d, x, nullptr, s);  // v^{k+1} into x
     if (e != hipSuccess) return e;
