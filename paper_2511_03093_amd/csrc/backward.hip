@@ -440,33 +440,45 @@ __global__ __launch_bounds__(kThreads) void xupdate_bwd_ms(int N, double rho, do
     for (int r = 0; r < R; ++r) m |= ((bits[((size_t)r * H + h) * Wq + (w >> 5)] >> (w & 31)) & 1u) << r;
     auto xval = [&](int g) { return (double)fk[(size_t)g * HW + p] - (double)dk[(size_t)g * HW + p]; };
     double yb = 0.0;
-    msimpl::solve<R>(
+    struct Raw {
+      float fb[R], xb[R];
+    };
+    msimpl::solve<R, Raw>(
         m, N, rho, gamma, periodic_solve, HW, p, scratch,
-        [&](int j, int r) {
-          const size_t o = (size_t)(j * R + r) * HW + p;
-          return (double)fbar[o] + (xbar ? (double)xbar[o] : 0.0);
+        [&](int j, Raw& raw) {
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const size_t o = (size_t)(j * R + r) * HW + p;
+            raw.fb[r] = fbar[o];
+            raw.xb[r] = xbar ? xbar[o] : 0.f;
+          }
         },
-        [&](int g, double lam) {
-          const size_t o = (size_t)g * HW + p;
-          const int r = g % R;
-          if ((m >> r) & 1u) yb += lam;
-          if (r == R - 1) {
-            ybar[(size_t)(g / R) * HW + p] += (float)yb;
-            yb = 0.0;
+        [&](const Raw& raw, int r) { return (double)raw.fb[r] + (xbar ? (double)raw.xb[r] : 0.0); },
+        [&](int j, const double (&lamj)[R]) {
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const int g = j * R + r;
+            const double lam = lamj[r];
+            const size_t o = (size_t)g * HW + p;
+            if ((m >> r) & 1u) yb += lam;
+            if (r == R - 1) {
+              ybar[(size_t)j * HW + p] += (float)yb;
+              yb = 0.0;
+            }
+            const double xv = xval(g);
+            ar += lam * ((double)uk[o] - (double)dk[o] - xv);
+            double lx;
+            if (NR == 1) {
+              lx = 0.0;
+            } else if (periodic_lap) {
+              lx = 2.0 * xv - xval((g + NR - 1) % NR) - xval((g + 1) % NR);
+            } else {
+              lx = (g > 0 ? xv - xval(g - 1) : 0.0) + (g < NR - 1 ? xv - xval(g + 1) : 0.0);
+            }
+            ag -= lam * lx;
+            ubar[o] = (float)(rho * lam);
+            dbar[o] = (float)((double)fbar[o] - rho * lam);
           }
-          const double xv = xval(g);
-          ar += lam * ((double)uk[o] - (double)dk[o] - xv);
-          double lx;
-          if (NR == 1) {
-            lx = 0.0;
-          } else if (periodic_lap) {
-            lx = 2.0 * xv - xval((g + NR - 1) % NR) - xval((g + 1) % NR);
-          } else {
-            lx = (g > 0 ? xv - xval(g - 1) : 0.0) + (g < NR - 1 ? xv - xval(g + 1) : 0.0);
-          }
-          ag -= lam * lx;
-          ubar[o] = (float)(rho * lam);
-          dbar[o] = (float)((double)fbar[o] - rho * lam);
         });
   }
   double s = block_sum(ar);

@@ -27,24 +27,41 @@ __global__ __launch_bounds__(256) void xupdate_multishot(const uint32_t* __restr
     const float ur = u[g];
     return d_from_f ? d[g] - ur : d[g];
   };
-  auto rhs = [&](int j, int r) {
-    const size_t g = (size_t)(j * R + r) * HW + p;
-    const float ur = u[g];
-    const float dr = dual(g);
+  struct Raw {
+    float u[R], d[R], y;
+  };
+  auto fetch = [&](int j, Raw& raw) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const size_t g = (size_t)(j * R + r) * HW + p;
+      raw.u[r] = u[g];
+      raw.d[r] = d[g];
+    }
+    raw.y = y[(size_t)j * HW + p];
+  };
+  auto rhs = [&](const Raw& raw, int r) {
+    const float ur = raw.u[r];
+    const float dr = d_from_f ? raw.d[r] - ur : raw.d[r];
     double v = rho * ((double)ur - (double)dr);
-    if ((m >> r) & 1u) v += (double)y[(size_t)j * HW + p];
+    if ((m >> r) & 1u) v += (double)raw.y;
     return v;
   };
-  auto out = [&](int g, double xv) {
-    const size_t o = (size_t)g * HW + p;
-    const float dr = dual(o);
-    if (x_out) x_out[o] = (float)xv;
-    if (f_out) f_out[o] = (float)(xv + (double)dr);
+  auto out = [&](int j, const double (&xv)[R]) {
+    // the block's d values first (f_out may alias the d source), then the stores
+    float dr[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) dr[r] = dual((size_t)(j * R + r) * HW + p);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const size_t o = (size_t)(j * R + r) * HW + p;
+      if (x_out) x_out[o] = (float)xv[r];
+      if (f_out) f_out[o] = (float)(xv[r] + (double)dr[r]);
+    }
   };
   if constexpr (LDS)
-    msimpl::solve<R>(m, N, rho, gamma, periodic, blockDim.x, threadIdx.x, lds_scratch, rhs, out);
+    msimpl::solve<R, Raw>(m, N, rho, gamma, periodic, blockDim.x, threadIdx.x, lds_scratch, fetch, rhs, out);
   else
-    msimpl::solve<R>(m, N, rho, gamma, periodic, HW, p, scratch, rhs, out);
+    msimpl::solve<R, Raw>(m, N, rho, gamma, periodic, HW, p, scratch, fetch, rhs, out);
 }
 
 template <int... Rs>

@@ -31,24 +31,30 @@ __device__ __forceinline__ void thomas(const double (&l)[R], const double (&invd
   for (int i = R - 2; i >= 0; --i) v[i] = fma(-l[i + 1], v[i + 1], v[i] * invd[i]);
 }
 
-// rhs(j, r) -> double: entry (j R + r) of the right-hand side.
-// out(g, x) is called once per slice g = 0..NR-1 in order with the solution's entry.
+// Right-hand side in two steps: fetch(j, raw) issues the loads of block j into the
+// caller's Raw record, rhs(raw, r) -> double forms entry (j R + r) from it.  Block
+// j + 1 is fetched before block j is eliminated, so its loads overlap that work.
+// out(j, x_j) is called once per block j = 0..N-1 in order with the block's R entries.
 // scratch: three [NR][stride] double arrays; this pixel's column is q (an HBM volume
 // with stride H W and q the pixel, or an LDS block with stride = threads and q the lane).
-template <int R, typename Rhs, typename Out>
+template <int R, typename Raw, typename Fetch, typename Rhs, typename Out>
 __device__ __forceinline__ void solve(uint32_t m, int N, double rho, double gamma, int periodic, size_t stride, size_t q,
-                                      double* __restrict__ scratch, Rhs&& rhs, Out&& out) {
+                                      double* __restrict__ scratch, Fetch&& fetch, Rhs&& rhs, Out&& out) {
   const int NR = N * R;
   const size_t HW = stride, p = q;
   double* Yb = scratch;                    // [NR][stride]
   double* Zs = scratch + (size_t)NR * HW;  // [NR][stride]
   double* Yw = scratch + 2 * (size_t)NR * HW;
   double sigma = 0.0, carry_b = 0.0, carry_w = 0.0;
+  Raw raw_next;
+  fetch(0, raw_next);
   for (int j = 0; j < N; ++j) {
+    const Raw raw = raw_next;
+    if (j + 1 < N) fetch(j + 1, raw_next);
     double bb[R], bw[R], l[R], invd[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      bb[r] = rhs(j, r);
+      bb[r] = rhs(raw, r);
       bw[r] = 0.0;
     }
     bb[0] += carry_b;
@@ -132,11 +138,17 @@ __device__ __forceinline__ void solve(uint32_t m, int N, double rho, double gamm
   }
   double coef = 0.0;
   if (periodic) coef = gamma * (xb_first - xb_last) / (1.0 + gamma * (xw_first - xw_last));
-  for (int g = 0; g < NR; ++g) {
-    const size_t o = (size_t)g * HW + p;
-    double xv = Yb[o];
-    if (periodic) xv -= coef * Yw[o];
-    out(g, xv);
+  // the solution block by block: out(j, x_j) sees all R entries of block j at once, so
+  // its own loads for the block can be issued together
+  for (int j = 0; j < N; ++j) {
+    double xv[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const size_t o = (size_t)(j * R + r) * HW + p;
+      xv[r] = Yb[o];
+      if (periodic) xv[r] -= coef * Yw[o];
+    }
+    out(j, xv);
   }
 }
 
