@@ -77,7 +77,9 @@ enum { CSPNP_WS_SOLVE = 0, CSPNP_WS_DENOISE = 1, CSPNP_WS_SOLVE_TOL = 2 };
 typedef struct cspnp_desc {
   int32_t H, W;
   int32_t R;        /* compression ratio, 1..32 */
-  int32_t N;        /* shots per volume, N*R <= 1024 (N > 1: no backward, no batching) */
+  int32_t N;        /* shots per volume, N*R <= 1024 (N > 1: not batched; the x-step then
+                       uses an FP64 scratch volume the plan owns, so calls on one such
+                       plan must not overlap) */
   int32_t zbc;      /* CSPNP_ZBC_* */
   int32_t denoiser; /* CSPNP_DENOISER_* */
 } cspnp_desc;
@@ -217,7 +219,7 @@ int cspnp_bm3d_layout(const cspnp_plan* plan, size_t* matches_offset, size_t* co
  * rho, lambda, gamma.  (The paper defines no gradient: this differentiates the
  * iteration this library runs.)  TV (tv_inner <= 16) and Tikhonov denoisers,
  * any number of shots N (N > 1 uses the plan's block-elimination scratch, so
- * the backward of a plan must not overlap another call on the same plan).
+ * calls on such a plan must not overlap).
  * Other denoisers: CSPNP_EUNSUPPORTED. */
 
 /* Bytes of the checkpoint buffer: ceil(iters/ckpt_every) x (u, d) volumes. */

@@ -444,7 +444,7 @@ __global__ __launch_bounds__(kThreads) void xupdate_bwd_ms(int N, double rho, do
       float fb[R], xb[R];
     };
     msimpl::solve<R, Raw>(
-        m, N, rho, gamma, periodic_solve, HW, p, scratch,
+        m, N, rho, gamma, periodic_solve, HW, p, scratch, scratch + 2 * (size_t)NR * HW, HW, p,
         [&](int j, Raw& raw) {
 #pragma unroll
           for (int r = 0; r < R; ++r) {

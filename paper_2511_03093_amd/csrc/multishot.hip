@@ -7,8 +7,10 @@ namespace cspnp {
 
 namespace {
 
-// LDS: the forward vectors of a wave's 64 pixels live in LDS ([3][NR][64] doubles)
-// when they fit, else in the plan's HBM scratch volume.
+// LDS: the forward vectors y and z of a wave's 64 pixels live in LDS ([2][NR][64]
+// doubles) when they fit, else in the plan's HBM scratch volume; the periodic wrap's
+// vectors are always in that volume (LDS for two arrays lets three workgroups share
+// a CU: at 200x200 pixels every wave is then resident at once).
 template <int R, bool LDS>
 __global__ __launch_bounds__(256) void xupdate_multishot(const uint32_t* __restrict__ bits, int H, int W, int Wq,
                                                          int N, double rho, double gamma, int periodic,
@@ -58,10 +60,12 @@ __global__ __launch_bounds__(256) void xupdate_multishot(const uint32_t* __restr
       if (f_out) f_out[o] = (float)(xv[r] + (double)dr[r]);
     }
   };
+  double* const yw = scratch + 2 * (size_t)N * R * HW;  // the wrap's array: HBM on both paths
   if constexpr (LDS)
-    msimpl::solve<R, Raw>(m, N, rho, gamma, periodic, blockDim.x, threadIdx.x, lds_scratch, fetch, rhs, out);
+    msimpl::solve<R, Raw>(m, N, rho, gamma, periodic, blockDim.x, threadIdx.x, lds_scratch, yw, HW, p, fetch, rhs,
+                          out);
   else
-    msimpl::solve<R, Raw>(m, N, rho, gamma, periodic, HW, p, scratch, fetch, rhs, out);
+    msimpl::solve<R, Raw>(m, N, rho, gamma, periodic, HW, p, scratch, yw, HW, p, fetch, rhs, out);
 }
 
 template <int... Rs>
@@ -77,7 +81,7 @@ using AllR = RTab<1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18,
                   28, 29, 30, 31, 32>;
 
 constexpr int kLdsLanes = 64;                     // one wave per workgroup on the LDS path
-constexpr size_t kMaxLdsScratch = 80 * 1024;      // N R <= 53: two workgroups per CU
+constexpr size_t kMaxLdsScratch = 80 * 1024;      // N R <= 80: at least two workgroups per CU
 
 }  // namespace
 
@@ -87,7 +91,7 @@ size_t multishot_scratch_bytes(const cspnp_desc& de) {
   return de.N > 1 ? 3 * (size_t)de.N * de.R * de.H * de.W * sizeof(double) : 0;
 }
 
-size_t multishot_lds_bytes(const cspnp_desc& de) { return 3 * (size_t)de.N * de.R * kLdsLanes * sizeof(double); }
+size_t multishot_lds_bytes(const cspnp_desc& de) { return 2 * (size_t)de.N * de.R * kLdsLanes * sizeof(double); }
 
 hipError_t launch_xupdate_multishot(const cspnp_plan& pl, double rho, double gamma, const float* y, const float* u,
                                     const float* d, bool d_from_f, float* x_out, float* f_out, hipStream_t s) {
@@ -102,7 +106,7 @@ hipError_t launch_xupdate_multishot(const cspnp_plan& pl, double rho, double gam
       // one wave per workgroup, its pixels' forward vectors in LDS
       hipLaunchKernelGGL((xupdate_multishot<R, true>), dim3((unsigned)((HW + kLdsLanes - 1) / kLdsLanes)),
                          dim3(kLdsLanes), lds, s, pl.bits, de.H, de.W, pl.Wq, de.N, rho, gamma, periodic, y, u, d,
-                         d_from_f ? 1 : 0, x_out, f_out, nullptr);
+                         d_from_f ? 1 : 0, x_out, f_out, pl.ms_scratch);
     } else {
       hipLaunchKernelGGL((xupdate_multishot<R, false>), dim3((unsigned)((HW + 255) / 256)), dim3(256), 0, s, pl.bits,
                          de.H, de.W, pl.Wq, de.N, rho, gamma, periodic, y, u, d, d_from_f ? 1 : 0, x_out, f_out,

@@ -14,7 +14,8 @@
 // sweep stores y_j = S_j^{-1} b~_j and z_j = S_j^{-1} e_R, and the backward sweep
 // is x_j = y_j + gamma x_{j+1,1} z_j.  The wrap is a final Sherman-Morrison step
 // with a second right-hand side w.  Work O(N R) per pixel; the forward vectors
-// live in an FP64 scratch of 3 N R doubles per pixel (LDS or an HBM volume).
+// live in an FP64 scratch of 3 N R doubles per pixel (the first two in LDS or an HBM
+// volume, the wrap's in an HBM volume).
 #pragma once
 
 #include "common.hpp"
@@ -35,16 +36,19 @@ __device__ __forceinline__ void thomas(const double (&l)[R], const double (&invd
 // caller's Raw record, rhs(raw, r) -> double forms entry (j R + r) from it.  Block
 // j + 1 is fetched before block j is eliminated, so its loads overlap that work.
 // out(j, x_j) is called once per block j = 0..N-1 in order with the block's R entries.
-// scratch: three [NR][stride] double arrays; this pixel's column is q (an HBM volume
-// with stride H W and q the pixel, or an LDS block with stride = threads and q the lane).
+// scratch: two [NR][stride] double arrays (y and z of the forward sweep); this
+// pixel's column is q (an HBM volume with stride H W and q the pixel, or an LDS
+// block with stride = threads and q the lane).  yw: the periodic wrap's third
+// array, [NR][yw_stride] at column yw_q (an HBM volume in every caller).
 template <int R, typename Raw, typename Fetch, typename Rhs, typename Out>
 __device__ __forceinline__ void solve(uint32_t m, int N, double rho, double gamma, int periodic, size_t stride, size_t q,
-                                      double* __restrict__ scratch, Fetch&& fetch, Rhs&& rhs, Out&& out) {
+                                      double* __restrict__ scratch, double* __restrict__ yw, size_t yw_stride,
+                                      size_t yw_q, Fetch&& fetch, Rhs&& rhs, Out&& out) {
   const int NR = N * R;
   const size_t HW = stride, p = q;
   double* Yb = scratch;                    // [NR][stride]
   double* Zs = scratch + (size_t)NR * HW;  // [NR][stride]
-  double* Yw = scratch + 2 * (size_t)NR * HW;
+  auto Yw = [&](int gi) -> double& { return yw[(size_t)gi * yw_stride + yw_q]; };
   double sigma = 0.0, carry_b = 0.0, carry_w = 0.0;
   Raw raw_next;
   fetch(0, raw_next);
@@ -108,7 +112,7 @@ __device__ __forceinline__ void solve(uint32_t m, int N, double rho, double gamm
       const size_t g = (size_t)(j * R + r) * HW + p;
       Yb[g] = bb[r];
       Zs[g] = er[r];
-      if (periodic) Yw[g] = bw[r];
+      if (periodic) Yw(j * R + r) = bw[r];
     }
     sigma = gamma * gamma * er[R - 1];
     carry_b = gamma * bb[R - 1];
@@ -127,14 +131,14 @@ __device__ __forceinline__ void solve(uint32_t m, int N, double rho, double gamm
       if (j == N - 1 && r == R - 1) xb_last = xb;
       if (j == 0 && r == 0) xb_first = xb;
       if (periodic) {
-        const double xw = Yw[g] + gamma * nw * z;
-        Yw[g] = xw;
+        const double xw = Yw(j * R + r) + gamma * nw * z;
+        Yw(j * R + r) = xw;
         if (j == N - 1 && r == R - 1) xw_last = xw;
         if (j == 0 && r == 0) xw_first = xw;
       }
     }
     nb = Yb[(size_t)(j * R) * HW + p];
-    if (periodic) nw = Yw[(size_t)(j * R) * HW + p];
+    if (periodic) nw = Yw(j * R);
   }
   double coef = 0.0;
   if (periodic) coef = gamma * (xb_first - xb_last) / (1.0 + gamma * (xw_first - xw_last));
@@ -146,7 +150,7 @@ __device__ __forceinline__ void solve(uint32_t m, int N, double rho, double gamm
     for (int r = 0; r < R; ++r) {
       const size_t o = (size_t)(j * R + r) * HW + p;
       xv[r] = Yb[o];
-      if (periodic) xv[r] -= coef * Yw[o];
+      if (periodic) xv[r] -= coef * Yw(j * R + r);
     }
     out(j, xv);
   }
