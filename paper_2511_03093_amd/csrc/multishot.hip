@@ -8,9 +8,10 @@ namespace cspnp {
 namespace {
 
 // LDS: the forward vectors y and z of a wave's 64 pixels live in LDS ([2][NR][64]
-// doubles) when they fit, else in the plan's HBM scratch volume; the periodic wrap's
-// vectors are always in that volume (LDS for two arrays lets three workgroups share
-// a CU: at 200x200 pixels every wave is then resident at once).
+// doubles, then the d values as [NR][64] floats) when they fit, else in the plan's
+// HBM scratch volume; the periodic wrap's vectors are always in that volume (LDS for
+// two arrays lets three workgroups share a CU: at 200x200 pixels every wave is then
+// resident at once).
 template <int R, bool LDS>
 __global__ __launch_bounds__(256) void xupdate_multishot(const uint32_t* __restrict__ bits, int H, int W, int Wq,
                                                          int N, double rho, double gamma, int periodic,
@@ -29,8 +30,13 @@ __global__ __launch_bounds__(256) void xupdate_multishot(const uint32_t* __restr
     const float ur = u[g];
     return d_from_f ? d[g] - ur : d[g];
   };
+  // LDS path: the d values of the lane's NR slices are kept in LDS after the
+  // [2][NR][64] doubles of the forward sweep, for the output (no second read of u, d)
+  const int NR = N * R;
+  float* const dl = reinterpret_cast<float*>(lds_scratch + 2 * (size_t)NR * blockDim.x);
   struct Raw {
     float u[R], d[R], y;
+    int j;
   };
   auto fetch = [&](int j, Raw& raw) {
 #pragma unroll
@@ -40,10 +46,12 @@ __global__ __launch_bounds__(256) void xupdate_multishot(const uint32_t* __restr
       raw.d[r] = d[g];
     }
     raw.y = y[(size_t)j * HW + p];
+    raw.j = j;
   };
   auto rhs = [&](const Raw& raw, int r) {
     const float ur = raw.u[r];
     const float dr = d_from_f ? raw.d[r] - ur : raw.d[r];
+    if constexpr (LDS) dl[(size_t)(raw.j * R + r) * blockDim.x + threadIdx.x] = dr;
     double v = rho * ((double)ur - (double)dr);
     if ((m >> r) & 1u) v += (double)raw.y;
     return v;
@@ -52,7 +60,8 @@ __global__ __launch_bounds__(256) void xupdate_multishot(const uint32_t* __restr
     // the block's d values first (f_out may alias the d source), then the stores
     float dr[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) dr[r] = dual((size_t)(j * R + r) * HW + p);
+    for (int r = 0; r < R; ++r)
+      dr[r] = LDS ? dl[(size_t)(j * R + r) * blockDim.x + threadIdx.x] : dual((size_t)(j * R + r) * HW + p);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const size_t o = (size_t)(j * R + r) * HW + p;
@@ -81,7 +90,7 @@ using AllR = RTab<1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18,
                   28, 29, 30, 31, 32>;
 
 constexpr int kLdsLanes = 64;                     // one wave per workgroup on the LDS path
-constexpr size_t kMaxLdsScratch = 80 * 1024;      // N R <= 80: at least two workgroups per CU
+constexpr size_t kMaxLdsScratch = 80 * 1024;      // N R <= 64: at least two workgroups per CU
 
 }  // namespace
 
@@ -91,7 +100,9 @@ size_t multishot_scratch_bytes(const cspnp_desc& de) {
   return de.N > 1 ? 3 * (size_t)de.N * de.R * de.H * de.W * sizeof(double) : 0;
 }
 
-size_t multishot_lds_bytes(const cspnp_desc& de) { return 2 * (size_t)de.N * de.R * kLdsLanes * sizeof(double); }
+size_t multishot_lds_bytes(const cspnp_desc& de) {
+  return (size_t)de.N * de.R * kLdsLanes * (2 * sizeof(double) + sizeof(float));
+}
 
 hipError_t launch_xupdate_multishot(const cspnp_plan& pl, double rho, double gamma, const float* y, const float* u,
                                     const float* d, bool d_from_f, float* x_out, float* f_out, hipStream_t s) {
