@@ -118,39 +118,71 @@ __device__ __forceinline__ void solve(uint32_t m, int N, double rho, double gamm
     carry_b = gamma * bb[R - 1];
     carry_w = gamma * bw[R - 1];
   }
-  // backward sweep, x_j = y_j + gamma x_{j+1,1} z_j (overwriting y in the scratch)
+  // backward sweep, x_j = y_j + gamma x_{j+1,1} z_j (overwriting y in the scratch).  The
+  // wrap's vector lives in global memory: block j - 1's entries are loaded while block
+  // j is worked on, and the output pass below prefetches the same way.
   double nb = 0.0, nw = 0.0;
   double xb_first = 0.0, xb_last = 0.0, xw_first = 0.0, xw_last = 0.0;
+  double ywn[R];
+  if (periodic) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) ywn[r] = Yw((N - 1) * R + r);
+  }
   for (int j = N - 1; j >= 0; --j) {
+    double ywc[R];
+    if (periodic) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) ywc[r] = ywn[r];
+      if (j > 0) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) ywn[r] = Yw((j - 1) * R + r);
+      }
+    }
+    double nb_next = 0.0, nw_next = 0.0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const size_t g = (size_t)(j * R + r) * HW + p;
       const double z = Zs[g];
       const double xb = Yb[g] + gamma * nb * z;
       Yb[g] = xb;
+      if (r == 0) nb_next = xb;
       if (j == N - 1 && r == R - 1) xb_last = xb;
       if (j == 0 && r == 0) xb_first = xb;
       if (periodic) {
-        const double xw = Yw(j * R + r) + gamma * nw * z;
+        const double xw = ywc[r] + gamma * nw * z;
         Yw(j * R + r) = xw;
+        if (r == 0) nw_next = xw;
         if (j == N - 1 && r == R - 1) xw_last = xw;
         if (j == 0 && r == 0) xw_first = xw;
       }
     }
-    nb = Yb[(size_t)(j * R) * HW + p];
-    if (periodic) nw = Yw(j * R);
+    nb = nb_next;
+    nw = nw_next;
   }
   double coef = 0.0;
   if (periodic) coef = gamma * (xb_first - xb_last) / (1.0 + gamma * (xw_first - xw_last));
   // the solution block by block: out(j, x_j) sees all R entries of block j at once, so
   // its own loads for the block can be issued together
+  if (periodic) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) ywn[r] = Yw(r);
+  }
   for (int j = 0; j < N; ++j) {
+    double ywc[R];
+    if (periodic) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) ywc[r] = ywn[r];
+      if (j + 1 < N) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) ywn[r] = Yw((j + 1) * R + r);
+      }
+    }
     double xv[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const size_t o = (size_t)(j * R + r) * HW + p;
       xv[r] = Yb[o];
-      if (periodic) xv[r] -= coef * Yw(j * R + r);
+      if (periodic) xv[r] -= coef * ywc[r];
     }
     out(j, xv);
   }
