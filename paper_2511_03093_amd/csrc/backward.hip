@@ -34,6 +34,8 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kGrid = 1024;  // fixed grid of the grid-stride kernels (one FP64 partial per block)
+constexpr int kMsLanes = 64;              // N > 1 x-step VJP: one wave per workgroup on the LDS path
+constexpr size_t kMsMaxLds = 80 * 1024;  // its LDS block: N R <= 64
 
 size_t align_up(size_t n) { return (n + 255) & ~size_t(255); }
 
@@ -419,9 +421,21 @@ __global__ __launch_bounds__(kThreads) void xupdate_bwd(const ZSolve z, int peri
   if (threadIdx.x == 0) part_gam[blockIdx.x] = s;
 }
 
+// Sum over one wave (blocks of 64 threads); lane 0 returns it.
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
 // The same for N > 1 shots: lam = A^{-1}(fbar + xbar) by the block elimination
 // (A symmetric), ybar_j += m . lam_j per shot, (L x) over the chain of all N R slices.
-template <int R>
+// LDS: one wave per workgroup keeps its pixels' forward vectors ([2][NR][64] doubles)
+// and the fbar values of the right-hand side ([NR][64] floats) in LDS; otherwise the
+// vectors live in the plan's HBM scratch volume (the periodic wrap's always does).
+// x^k = f - d is loaded once per slice: each block keeps its R values and the
+// neighbours across block boundaries are carried from the block before (and the
+// first block of the next one loaded ahead).
+template <int R, bool LDS>
 __global__ __launch_bounds__(kThreads) void xupdate_bwd_ms(int N, double rho, double gamma, int periodic_solve,
                                                            int periodic_lap, const uint32_t* __restrict__ bits, int H,
                                                            int W, int Wq, const float* __restrict__ fbar,
@@ -430,62 +444,94 @@ __global__ __launch_bounds__(kThreads) void xupdate_bwd_ms(int N, double rho, do
                                                            float* __restrict__ ybar, float* __restrict__ ubar,
                                                            float* __restrict__ dbar, double* __restrict__ part_rho,
                                                            double* __restrict__ part_gam, double* __restrict__ scratch) {
+  extern __shared__ double lds_scratch[];
   const size_t HW = (size_t)H * W;
   const int NR = N * R;
+  float* const fl = reinterpret_cast<float*>(lds_scratch + 2 * (size_t)NR * blockDim.x);
   double ar = 0.0, ag = 0.0;
-  for (size_t p = blockIdx.x * (size_t)kThreads + threadIdx.x; p < HW; p += (size_t)gridDim.x * kThreads) {
+  for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < HW; p += (size_t)gridDim.x * blockDim.x) {
     const int h = (int)(p / W), w = (int)(p % W);
     uint32_t m = 0;
 #pragma unroll
     for (int r = 0; r < R; ++r) m |= ((bits[((size_t)r * H + h) * Wq + (w >> 5)] >> (w & 31)) & 1u) << r;
     auto xval = [&](int g) { return (double)fk[(size_t)g * HW + p] - (double)dk[(size_t)g * HW + p]; };
-    double yb = 0.0;
     struct Raw {
       float fb[R], xb[R];
+      int j;
     };
-    msimpl::solve<R, Raw>(
-        m, N, rho, gamma, periodic_solve, HW, p, scratch, scratch + 2 * (size_t)NR * HW, HW, p,
-        [&](int j, Raw& raw) {
+    // x of the slice before the current block (periodic: the chain's last slice before block 0)
+    double x_before = (periodic_lap && NR > 1) ? xval(NR - 1) : 0.0, x_first = 0.0;
+    auto fetch = [&](int j, Raw& raw) {
 #pragma unroll
-          for (int r = 0; r < R; ++r) {
-            const size_t o = (size_t)(j * R + r) * HW + p;
-            raw.fb[r] = fbar[o];
-            raw.xb[r] = xbar ? xbar[o] : 0.f;
-          }
-        },
-        [&](const Raw& raw, int r) { return (double)raw.fb[r] + (xbar ? (double)raw.xb[r] : 0.0); },
-        [&](int j, const double (&lamj)[R]) {
+      for (int r = 0; r < R; ++r) {
+        const size_t o = (size_t)(j * R + r) * HW + p;
+        raw.fb[r] = fbar[o];
+        raw.xb[r] = xbar ? xbar[o] : 0.f;
+      }
+      raw.j = j;
+    };
+    auto rhs = [&](const Raw& raw, int r) {
+      if constexpr (LDS) fl[(size_t)(raw.j * R + r) * blockDim.x + threadIdx.x] = raw.fb[r];
+      return (double)raw.fb[r] + (xbar ? (double)raw.xb[r] : 0.0);
+    };
+    auto out = [&](int j, const double (&lamj)[R]) {
+      double xs[R], uv[R];
+      float fb[R];
 #pragma unroll
-          for (int r = 0; r < R; ++r) {
-            const int g = j * R + r;
-            const double lam = lamj[r];
-            const size_t o = (size_t)g * HW + p;
-            if ((m >> r) & 1u) yb += lam;
-            if (r == R - 1) {
-              ybar[(size_t)j * HW + p] += (float)yb;
-              yb = 0.0;
-            }
-            const double xv = xval(g);
-            ar += lam * ((double)uk[o] - (double)dk[o] - xv);
-            double lx;
-            if (NR == 1) {
-              lx = 0.0;
-            } else if (periodic_lap) {
-              lx = 2.0 * xv - xval((g + NR - 1) % NR) - xval((g + 1) % NR);
-            } else {
-              lx = (g > 0 ? xv - xval(g - 1) : 0.0) + (g < NR - 1 ? xv - xval(g + 1) : 0.0);
-            }
-            ag -= lam * lx;
-            ubar[o] = (float)(rho * lam);
-            dbar[o] = (float)((double)fbar[o] - rho * lam);
-          }
-        });
+      for (int r = 0; r < R; ++r) {
+        const size_t o = (size_t)(j * R + r) * HW + p;
+        xs[r] = xval(j * R + r);
+        uv[r] = (double)uk[o] - (double)dk[o];
+        fb[r] = LDS ? fl[(size_t)(j * R + r) * blockDim.x + threadIdx.x] : fbar[o];
+      }
+      if (j == 0) x_first = xs[0];
+      // x of the slice after the block: the next block's first, or (periodic) the chain's first
+      const double x_after = j + 1 < N ? xval((j + 1) * R) : (periodic_lap ? x_first : 0.0);
+      double yb = 0.0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int g = j * R + r;
+        const double lam = lamj[r];
+        const size_t o = (size_t)g * HW + p;
+        if ((m >> r) & 1u) yb += lam;
+        const double xv = xs[r];
+        ar += lam * (uv[r] - xv);
+        const double xm = r > 0 ? xs[r - 1] : x_before, xp = r < R - 1 ? xs[r + 1] : x_after;
+        double lx;
+        if (NR == 1) {
+          lx = 0.0;
+        } else if (periodic_lap) {
+          lx = 2.0 * xv - xm - xp;
+        } else {
+          lx = (g > 0 ? xv - xm : 0.0) + (g < NR - 1 ? xv - xp : 0.0);
+        }
+        ag -= lam * lx;
+        ubar[o] = (float)(rho * lam);
+        dbar[o] = (float)((double)fb[r] - rho * lam);
+      }
+      ybar[(size_t)j * HW + p] += (float)yb;
+      x_before = xs[R - 1];
+    };
+    double* const yw = scratch + 2 * (size_t)NR * HW;
+    if constexpr (LDS)
+      msimpl::solve<R, Raw>(m, N, rho, gamma, periodic_solve, blockDim.x, threadIdx.x, lds_scratch, yw, HW, p, fetch,
+                            rhs, out);
+    else
+      msimpl::solve<R, Raw>(m, N, rho, gamma, periodic_solve, HW, p, scratch, yw, HW, p, fetch, rhs, out);
   }
-  double s = block_sum(ar);
-  if (threadIdx.x == 0) part_rho[blockIdx.x] = s;
-  __syncthreads();
-  s = block_sum(ag);
-  if (threadIdx.x == 0) part_gam[blockIdx.x] = s;
+  if constexpr (LDS) {
+    const double s = wave_sum(ar), t = wave_sum(ag);
+    if (threadIdx.x == 0) {
+      part_rho[blockIdx.x] = s;
+      part_gam[blockIdx.x] = t;
+    }
+  } else {
+    double s = block_sum(ar);
+    if (threadIdx.x == 0) part_rho[blockIdx.x] = s;
+    __syncthreads();
+    s = block_sum(ag);
+    if (threadIdx.x == 0) part_gam[blockIdx.x] = s;
+  }
 }
 
 // acc[slot] += sum(partial[0..n)) in a fixed order
@@ -688,9 +734,18 @@ hipError_t enqueue_backward(const cspnp_plan& pl, const cspnp_params& p, const f
                              part, part + kGrid);
         } else {
           const int periodic_solve = (periodic_lap && de.N * de.R >= 2 && p.gamma > 0) ? 1 : 0;
-          hipLaunchKernelGGL(xupdate_bwd_ms<R>, G, B, 0, s, de.N, p.rho, p.gamma, periodic_solve, periodic_lap,
-                             pl.bits, de.H, de.W, pl.Wq, fbar, k == K - 1 ? xbar : nullptr, V(L.off_seg_u, i),
-                             V(L.off_seg_d, i), fk, ybar, ubar, dbar, part, part + kGrid, pl.ms_scratch);
+          // kGrid workgroups either way: reduce_into sums kGrid partials
+          const size_t lds = (size_t)de.N * de.R * kMsLanes * (2 * sizeof(double) + sizeof(float));
+          if (lds <= kMsMaxLds)
+            hipLaunchKernelGGL((xupdate_bwd_ms<R, true>), G, dim3(kMsLanes), lds, s, de.N, p.rho, p.gamma,
+                               periodic_solve, periodic_lap, pl.bits, de.H, de.W, pl.Wq, fbar,
+                               k == K - 1 ? xbar : nullptr, V(L.off_seg_u, i), V(L.off_seg_d, i), fk, ybar, ubar,
+                               dbar, part, part + kGrid, pl.ms_scratch);
+          else
+            hipLaunchKernelGGL((xupdate_bwd_ms<R, false>), G, B, 0, s, de.N, p.rho, p.gamma, periodic_solve,
+                               periodic_lap, pl.bits, de.H, de.W, pl.Wq, fbar, k == K - 1 ? xbar : nullptr,
+                               V(L.off_seg_u, i), V(L.off_seg_d, i), fk, ybar, ubar, dbar, part, part + kGrid,
+                               pl.ms_scratch);
         }
         return hipGetLastError();
       }));
